@@ -1,0 +1,162 @@
+/*
+ * pwa.h -- C ABI of the MI355X (gfx950) partial-wave-analysis likelihood library.
+ *
+ * The library evaluates the unbinned negative log-likelihood of a partial
+ * wave analysis and its gradient with respect to the complex production
+ * amplitudes V, over precomputed complex decay amplitudes A (Berger, "Partial
+ * Wave Analysis using Graphics Cards", Section 2):
+ *
+ *   Eq. 1   I(Omega) = | sum_a V_a A_a(Omega) |^2
+ *   Eq. 2   -ln L = -sum_{i in data} ln I_i + N_D ln S,
+ *           S = (1/N_gen) sum_{j in accepted MC} w_j I_j
+ *           (MC normalisation integral; weights per the footnote on
+ *           non-uniform MC; N_gen counts generated events, acceptance is
+ *           expressed by supplying only accepted MC rows)
+ *   Eq. 3   extended form: -ln L = -sum ln I_i + S
+ *           and its bracket M_ab = (1/N_gen) sum_j w_j conj(A_ja) A_jb, which
+ *           can be precomputed while only V varies, giving S = V^H M V.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Complex arrays are interleaved (re, im) in the context's precision.  A
+ * sample of n events with k waves is row-major: event i, wave a at complex
+ * index i*ld + a (ld >= k).
+ *
+ * V is always FP64 on the host for the synchronous calls: 2k doubles
+ * (Re V_0, Im V_0, Re V_1, ...).  The gradient has the same layout and holds
+ * dNLL/dRe V_a and dNLL/dIm V_a (minimisers see real parameters only, Section
+ * 4, "Fits with complex parameters").  Equivalently grad = 2 (Re g, Im g) with
+ * g the Wirtinger derivative dNLL/d conj(V).
+ *
+ * Precision: PWA_F32 keeps amplitudes in single precision and computes each
+ * event's z, I, ln I and z/I in single precision, with every sum over events
+ * in double precision (the paper's remark on precision in Section 2).  PWA_F64
+ * is double precision throughout.
+ *
+ * Errors: every call returns a pwa_status.  On an error nothing is written to
+ * the caller's outputs, except PWA_E_DOMAIN, which writes NLL = +inf (and an
+ * unspecified gradient) so a minimiser can reject the step.  Calls never
+ * abort, print or throw; pwa_last_error() describes the last failure.
+ *
+ * Concurrency: a context is not thread-safe.  All its device work is ordered
+ * on its stream.  The synchronous calls wait on that stream; the _async calls
+ * neither wait nor allocate, so they can be captured into a HIP graph.
+ */
+#ifndef PWA_H
+#define PWA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pwa_ctx pwa_ctx;
+
+typedef enum {
+    PWA_OK = 0,
+    PWA_E_INVAL = 1,        /* bad argument (null pointer, size, k mismatch, ...) */
+    PWA_E_NOMEM = 2,        /* device or pinned host allocation failed */
+    PWA_E_HIP = 3,          /* a HIP runtime call or kernel launch failed */
+    PWA_E_DOMAIN = 4,       /* some data I <= 0, S <= 0 or a non-finite value: NLL = +inf */
+    PWA_E_STATE = 5,        /* call needs samples that have not been set */
+    PWA_E_UNSUPPORTED = 6   /* valid request this build does not implement (e.g. k > 64) */
+} pwa_status;
+
+typedef enum { PWA_F32 = 0, PWA_F64 = 1 } pwa_prec;
+typedef enum { PWA_DATA = 0, PWA_MC = 1 } pwa_set;
+typedef enum { PWA_MC_STREAM = 0, PWA_MC_GRAM = 1 } pwa_mc_mode;
+typedef enum { PWA_HOST = 0, PWA_DEVICE = 1 } pwa_where;
+
+/* Largest number of waves a context accepts. */
+#define PWA_MAX_K 64
+
+/* Create a context on HIP device `device` with amplitude precision `prec`.
+ * `stream` is a hipStream_t to order all work on, or NULL for a stream the
+ * context creates and owns.  A borrowed stream must outlive the context.
+ * *out receives the context.  Errors: PWA_E_INVAL (null out, bad prec or
+ * device), PWA_E_HIP, PWA_E_NOMEM. */
+pwa_status pwa_create(pwa_ctx **out, int device, pwa_prec prec, void *stream);
+
+/* Free every device and host resource of the context.  NULL is accepted. */
+pwa_status pwa_destroy(pwa_ctx *ctx);
+
+/* Store one sample (data or MC; Eq. 2's two sums).
+ *   A      n x k complex in the context's precision, row stride ld complex,
+ *          on the host or the device as `where` says.  The library copies it
+ *          into its own padded device layout; the caller may free A when the
+ *          call returns.
+ *   n      number of events (0 allowed)
+ *   k      number of waves, 1..PWA_MAX_K; data and MC must agree
+ *   w      MC only: n per-event weights in the context's precision, in the
+ *          same memory space as A, or NULL for unit weights (footnote on
+ *          weighted MC).  Must be NULL for the data sample.
+ *   n_gen  MC only: number of generated events N_gen of Eq. 3's 1/N_gen;
+ *          <= 0 means n.  Ignored for data.
+ * Replacing a sample whose k differs from the other sample's drops the other
+ * sample.  Errors: PWA_E_INVAL, PWA_E_NOMEM, PWA_E_HIP, PWA_E_UNSUPPORTED. */
+pwa_status pwa_set_amplitudes(pwa_ctx *ctx, pwa_set which, const void *A, int64_t n,
+                              int32_t k, int64_t ld, pwa_where where, const void *w,
+                              double n_gen);
+
+/* Select how the normalisation is evaluated and which likelihood form is used.
+ *   mode      PWA_MC_STREAM: stream the MC rows on every evaluation.
+ *             PWA_MC_GRAM: precompute M (Eq. 3 bracket, FP64, k x k) once from
+ *             the MC rows; each evaluation then streams only the data rows
+ *             and uses S = V^H M V.
+ *   extended  0: Eq. 2 form (N_D ln S), 1: Eq. 3 form (+S).
+ * Errors: PWA_E_INVAL. */
+pwa_status pwa_set_mc_mode(pwa_ctx *ctx, pwa_mc_mode mode, int extended);
+
+/* NLL at V (host, 2k doubles) into *nll.  Waits for the result.
+ * Errors: PWA_E_INVAL, PWA_E_STATE (a sample missing; N_D = 0 needs no MC
+ * and gives NLL = 0 in the Eq. 2 form), PWA_E_DOMAIN, PWA_E_HIP. */
+pwa_status pwa_nll(pwa_ctx *ctx, const double *V, double *nll);
+
+/* NLL and gradient (host, 2k doubles) at V.  One fused pass over the rows.
+ * Errors as pwa_nll. */
+pwa_status pwa_nll_grad(pwa_ctx *ctx, const double *V, double *nll, double *grad);
+
+/* Device-side variant of pwa_nll_grad for graph capture and device minimisers.
+ *   V_dev    device pointer, 2k doubles, read when the kernel runs
+ *   out_dev  device pointer, 2k + 2 doubles, written when the kernel runs:
+ *            [0] NLL (+inf on a domain failure), [1 .. 2k] gradient,
+ *            [2k + 1] status flags (0 = ok, nonzero = PWA_E_DOMAIN)
+ * Enqueues on the context's stream and returns; no wait, no allocation.
+ * Errors (detected on the host only): PWA_E_INVAL, PWA_E_STATE, PWA_E_HIP. */
+pwa_status pwa_nll_grad_async(pwa_ctx *ctx, const double *V_dev, double *out_dev);
+
+/* NLL (and optionally gradients) for nv production vectors in one pass over
+ * the events (many fits / many starting points, Section 2 on repeated fits).
+ *   V      host, nv x 2k doubles (row b is V_b as above)
+ *   nll    host, nv doubles
+ *   grad   host, nv x 2k doubles, or NULL for NLL only
+ *   split  arithmetic of the dense contraction:
+ *            0  FP32 vector arithmetic (reference path of the batched call)
+ *            2  two-term FP16 split of A, V and the adjoint weights on matrix
+ *               cores (FP32 accumulation)
+ *            3  three-term BF16 split on matrix cores
+ * Errors as pwa_nll; PWA_E_UNSUPPORTED for an FP64 context with split != 0. */
+pwa_status pwa_nll_batch(pwa_ctx *ctx, int32_t nv, const double *V, double *nll,
+                         double *grad, int32_t split);
+
+/* Status flags of the last synchronous evaluation (0 = none). */
+pwa_status pwa_last_flags(pwa_ctx *ctx, uint32_t *flags);
+
+/* Message for the last failing call on this context (or on a NULL context). */
+const char *pwa_last_error(const pwa_ctx *ctx);
+
+/* Row stride (complex elements) of the library's device layout for k waves. */
+pwa_status pwa_layout_ld(pwa_ctx *ctx, int32_t k, int64_t *ld);
+
+/* Kernel timing: average duration in ms of the last `count` single-V kernel
+ * launches, measured with HIP events on the context's stream, when timing is
+ * enabled with pwa_set_timing(ctx, 1).  Timing adds an event pair per call. */
+pwa_status pwa_set_timing(pwa_ctx *ctx, int enable);
+pwa_status pwa_kernel_time(pwa_ctx *ctx, double *avg_ms, int64_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PWA_H */

@@ -1,0 +1,259 @@
+"""ctypes binding of libpwa.so (include/pwa.h): argument marshalling only.
+
+Every computation runs in the library's HIP kernels.  There is no CPU
+fallback: if the library is missing or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpwa.so")
+
+# status codes (pwa_status)
+OK, E_INVAL, E_NOMEM, E_HIP, E_DOMAIN, E_STATE, E_UNSUPPORTED = range(7)
+F32, F64 = 0, 1
+DATA, MC = 0, 1
+MC_STREAM, MC_GRAM = 0, 1
+HOST, DEVICE = 0, 1
+MAX_K = 64
+
+# every entry point declared in include/pwa.h
+EXPORTS = [
+    "pwa_create", "pwa_destroy", "pwa_set_amplitudes", "pwa_set_mc_mode", "pwa_nll",
+    "pwa_nll_grad", "pwa_nll_grad_async", "pwa_nll_batch", "pwa_last_flags", "pwa_last_error",
+    "pwa_layout_ld", "pwa_set_timing", "pwa_kernel_time",
+]
+
+
+class PwaError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"pwa status {status}: {message}")
+        self.status = status
+        self.message = message
+
+
+class DomainError(PwaError):
+    """NLL = +inf: a data intensity or the normalisation is not positive."""
+
+
+_lib = None
+
+
+def _hip_runtime_of_torch() -> Optional[str]:
+    """Path of the HIP runtime bundled with PyTorch, if PyTorch is installed."""
+    import importlib.util
+    spec = importlib.util.find_spec("torch")
+    if spec is None or not spec.submodule_search_locations:
+        return None
+    p = os.path.join(list(spec.submodule_search_locations)[0], "lib", "libamdhip64.so")
+    return p if os.path.exists(p) else None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (raises if it has not been built).
+
+    A process must hold one HIP runtime so that streams and device pointers
+    can pass between PyTorch and this library.  PyTorch ships its own
+    libamdhip64 (same soname as the system one, different file), so that file
+    is loaded first when PyTorch is installed; the library's dependency on
+    the soname then resolves to it, whichever of the two is imported first.
+    """
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build it with paper_1108_5882_amd.build.build()")
+    rt = _hip_runtime_of_torch()
+    if rt is not None:
+        ctypes.CDLL(rt, mode=ctypes.RTLD_GLOBAL)
+    lib = ctypes.CDLL(path)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    st = ctypes.c_int
+    sig = {
+        "pwa_create": [ctypes.POINTER(P), ctypes.c_int, ctypes.c_int, P],
+        "pwa_destroy": [P],
+        "pwa_set_amplitudes": [P, ctypes.c_int, P, I64, I32, I64, ctypes.c_int, P, D],
+        "pwa_set_mc_mode": [P, ctypes.c_int, ctypes.c_int],
+        "pwa_nll": [P, P, P],
+        "pwa_nll_grad": [P, P, P, P],
+        "pwa_nll_grad_async": [P, P, P],
+        "pwa_nll_batch": [P, I32, P, P, P, I32],
+        "pwa_last_flags": [P, ctypes.POINTER(ctypes.c_uint32)],
+        "pwa_layout_ld": [P, I32, ctypes.POINTER(I64)],
+        "pwa_set_timing": [P, ctypes.c_int],
+        "pwa_kernel_time": [P, ctypes.POINTER(D), ctypes.POINTER(I64)],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = st
+    lib.pwa_last_error.argtypes = [P]
+    lib.pwa_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)    # torch.cuda.Stream
+
+
+class Context:
+    """One likelihood context on one GPU (pwa_ctx).
+
+    precision: "f32" (FP32 amplitudes, FP64 sums) or "f64".
+    stream: torch.cuda.Stream, raw hipStream_t int, or None for a private stream.
+    """
+
+    def __init__(self, device: int = 0, precision: str = "f32", stream=None):
+        self.lib = load()
+        self.prec = {"f32": F32, "f64": F64}[precision]
+        self.real = np.float32 if self.prec == F32 else np.float64
+        self.cplx = np.complex64 if self.prec == F32 else np.complex128
+        self._stream_obj = stream          # keep a torch stream alive
+        h = ctypes.c_void_p()
+        s = _stream_handle(stream)
+        self._check(self.lib.pwa_create(ctypes.byref(h), device, self.prec,
+                                        None if s is None else ctypes.c_void_p(s)), None)
+        self.h = h
+        self.k = None
+
+    # ------------------------------------------------------------ helpers
+    def _check(self, status: int, h=-1):
+        if status == OK:
+            return
+        msg = self.lib.pwa_last_error(self.h if h == -1 else h)
+        msg = msg.decode() if msg else ""
+        cls = DomainError if status == E_DOMAIN else PwaError
+        raise cls(status, msg)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.pwa_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ------------------------------------------------------------ samples
+    def set_amplitudes(self, which: str, A, w=None, n_gen: Optional[float] = None):
+        """which: "data" or "mc".  A: numpy [n, k] complex (host) or a torch cuda
+        tensor [n, k] complex (device); w: matching weights or None."""
+        wh = {"data": DATA, "mc": MC}[which]
+        if _is_torch(A):
+            if A.dim() != 2:
+                raise ValueError("A must be [n, k]")
+            n, k = A.shape
+            ld = A.stride(0)
+            if A.stride(1) != 1:
+                raise ValueError("A must have unit stride along k")
+            if A.dtype != {F32: __import__("torch").complex64, F64: __import__("torch").complex128}[self.prec]:
+                raise TypeError("A dtype does not match the context precision")
+            wp = None
+            if w is not None:
+                if not w.is_contiguous() or w.numel() != n:
+                    raise ValueError("w must be contiguous [n]")
+                wp = ctypes.c_void_p(w.data_ptr())
+            self._check(self.lib.pwa_set_amplitudes(self.h, wh, ctypes.c_void_p(A.data_ptr()), n, k, ld,
+                                                    DEVICE, wp, float(n_gen or 0.0)))
+        else:
+            A = np.ascontiguousarray(A, dtype=self.cplx)
+            if A.ndim != 2:
+                raise ValueError("A must be [n, k]")
+            n, k = A.shape
+            wa = None if w is None else np.ascontiguousarray(w, dtype=self.real)
+            if wa is not None and wa.shape != (n,):
+                raise ValueError("w must be [n]")
+            self._check(self.lib.pwa_set_amplitudes(self.h, wh, _ptr(A), n, k, k, HOST, _ptr(wa),
+                                                    float(n_gen or 0.0)))
+        self.k = k
+
+    def set_mc_mode(self, mode: str = "stream", extended: bool = False):
+        self._check(self.lib.pwa_set_mc_mode(self.h, {"stream": MC_STREAM, "gram": MC_GRAM}[mode],
+                                             int(bool(extended))))
+
+    # --------------------------------------------------------- evaluation
+    def _v(self, V) -> np.ndarray:
+        V = np.asarray(V)
+        if np.iscomplexobj(V):
+            out = np.empty(2 * V.size)
+            out[0::2], out[1::2] = V.real, V.imag
+            return out
+        return np.ascontiguousarray(V, dtype=np.float64)
+
+    def nll(self, V) -> float:
+        v = self._v(V)
+        out = np.zeros(1)
+        self._check(self.lib.pwa_nll(self.h, _ptr(v), _ptr(out)))
+        return float(out[0])
+
+    def nll_grad(self, V):
+        """(NLL, gradient[2k]) with gradient = (dNLL/dRe V_a, dNLL/dIm V_a) interleaved."""
+        v = self._v(V)
+        out = np.zeros(1)
+        g = np.zeros(v.size)
+        self._check(self.lib.pwa_nll_grad(self.h, _ptr(v), _ptr(out), _ptr(g)))
+        return float(out[0]), g
+
+    def nll_grad_async(self, V_dev, out_dev):
+        """V_dev: torch cuda float64 [2k]; out_dev: torch cuda float64 [2k+2]."""
+        self._check(self.lib.pwa_nll_grad_async(self.h, ctypes.c_void_p(V_dev.data_ptr()),
+                                                ctypes.c_void_p(out_dev.data_ptr())))
+
+    def nll_batch(self, Vs, grad: bool = True, split: int = 0):
+        Vs = np.asarray(Vs)
+        if np.iscomplexobj(Vs):
+            v = np.empty((Vs.shape[0], 2 * Vs.shape[1]))
+            v[:, 0::2], v[:, 1::2] = Vs.real, Vs.imag
+        else:
+            v = np.ascontiguousarray(Vs, dtype=np.float64)
+        nv = v.shape[0]
+        nll = np.zeros(nv)
+        g = np.zeros_like(v) if grad else None
+        self._check(self.lib.pwa_nll_batch(self.h, nv, _ptr(v), _ptr(nll), _ptr(g), int(split)))
+        return (nll, g) if grad else nll
+
+    def last_flags(self) -> int:
+        f = ctypes.c_uint32()
+        self._check(self.lib.pwa_last_flags(self.h, ctypes.byref(f)))
+        return int(f.value)
+
+    def layout_ld(self, k: int) -> int:
+        ld = ctypes.c_int64()
+        self._check(self.lib.pwa_layout_ld(self.h, k, ctypes.byref(ld)))
+        return int(ld.value)
+
+    def set_timing(self, enable: bool):
+        self._check(self.lib.pwa_set_timing(self.h, int(bool(enable))))
+
+    def kernel_time(self):
+        """(average ms, count) of the single-V kernels launched since the last query."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._check(self.lib.pwa_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value

@@ -1,0 +1,464 @@
+// C ABI of the partial-wave likelihood library: context lifecycle, sample
+// staging into the device layout, and the evaluation entry points declared in
+// include/pwa.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace pwa;
+
+namespace {
+
+struct Sample {
+    void *A = nullptr;       // device rows, ld complex each
+    void *w = nullptr;       // device weights (MC) or null
+    int64_t n = 0;
+    double n_gen = 0.0;
+    bool set = false;
+};
+
+thread_local std::string g_err;
+
+}  // namespace
+
+struct pwa_ctx {
+    int device = 0;
+    pwa_prec prec = PWA_F32;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int cu_count = 0;
+
+    int32_t k = 0;
+    StreamShape shape{0, 0};
+    int64_t ld = 0;
+    Sample s[2];
+
+    pwa_mc_mode mode = PWA_MC_STREAM;
+    int extended = 0;
+    double *gram = nullptr;          // k x k complex FP64 (1/N_gen folded)
+    bool gram_valid = false;
+
+    int blocks_per_cu = 4;
+    double *partials = nullptr;
+    size_t partials_doubles = 0;
+    unsigned int *counter = nullptr;
+    double *out_dev = nullptr;       // [nll, grad[2k], flags]
+    double *out_host = nullptr;      // pinned copy target
+    uint32_t last_flags = 0;
+
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+
+    std::string err;
+};
+
+namespace {
+
+// Make the context's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+pwa_status fail(pwa_ctx *ctx, pwa_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx)
+        ctx->err = buf;
+    else
+        g_err = buf;
+    return st;
+}
+
+pwa_status hip_fail(pwa_ctx *ctx, hipError_t e, const char *what) {
+    return fail(ctx, e == hipErrorOutOfMemory ? PWA_E_NOMEM : PWA_E_HIP, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+#define PWA_HIP(ctx, call, what)                           \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+    } while (0)
+
+size_t elem_bytes(pwa_prec p) { return p == PWA_F32 ? sizeof(float) : sizeof(double); }
+
+void free_sample(Sample &s) {
+    if (s.A) (void)hipFree(s.A);
+    if (s.w) (void)hipFree(s.w);
+    s = Sample{};
+}
+
+// Grid for one evaluation: blocks per segment, at most what the rows need and
+// at most blocks_per_cu per compute unit overall, split in proportion to rows.
+void split_blocks(const pwa_ctx *ctx, int64_t n0, int64_t n1, int32_t nb[2]) {
+    const int rows_per_wave = stream_rows_per_wave(ctx->prec, ctx->shape);
+    const int waves_per_block = kStreamThreads / 64;
+    const int64_t rows_per_block = (int64_t)rows_per_wave * waves_per_block;
+    int64_t need[2] = {(n0 + rows_per_block - 1) / rows_per_block,
+                       (n1 + rows_per_block - 1) / rows_per_block};
+    const int64_t budget = (int64_t)ctx->cu_count * ctx->blocks_per_cu;
+    if (need[0] + need[1] <= budget) {
+        nb[0] = (int32_t)need[0];
+        nb[1] = (int32_t)need[1];
+        return;
+    }
+    const double frac = (double)n0 / (double)(n0 + n1);
+    int64_t b0 = (int64_t)std::llround(frac * (double)budget);
+    if (n0 > 0) b0 = std::max<int64_t>(b0, 1);
+    if (n1 > 0) b0 = std::min<int64_t>(b0, budget - 1);
+    b0 = std::min(b0, need[0]);
+    int64_t b1 = std::min(budget - b0, need[1]);
+    nb[0] = (int32_t)b0;
+    nb[1] = (int32_t)b1;
+}
+
+pwa_status ensure_gram(pwa_ctx *ctx) {
+    if (ctx->gram_valid) return PWA_OK;
+    const Sample &mc = ctx->s[1];
+    if (!ctx->gram) PWA_HIP(ctx, hipMalloc(&ctx->gram, sizeof(double) * 2 * PWA_MAX_K * PWA_MAX_K),
+                            "hipMalloc(gram)");
+    if (mc.n == 0) {
+        PWA_HIP(ctx, hipMemsetAsync(ctx->gram, 0, sizeof(double) * 2 * ctx->k * ctx->k, ctx->stream),
+                "hipMemsetAsync(gram)");
+    } else {
+        const int blocks = (int)std::min<int64_t>((int64_t)ctx->cu_count * 2, (mc.n + 63) / 64);
+        double *scratch = nullptr;
+        PWA_HIP(ctx, hipMalloc(&scratch, sizeof(double) * gram_partial_doubles(ctx->k, blocks)),
+                "hipMalloc(gram scratch)");
+        hipError_t e = launch_gram(ctx->prec, mc.A, mc.w, mc.n, ctx->ld, ctx->k, mc.n_gen, scratch,
+                                   blocks, ctx->gram, ctx->stream);
+        hipError_t e2 = hipStreamSynchronize(ctx->stream);
+        (void)hipFree(scratch);
+        if (e != hipSuccess) return hip_fail(ctx, e, "gram kernel");
+        if (e2 != hipSuccess) return hip_fail(ctx, e2, "gram kernel");
+    }
+    ctx->gram_valid = true;
+    return PWA_OK;
+}
+
+// Validates state and fills the launch arguments; *blocks = 0 means nothing to launch.
+pwa_status prepare(pwa_ctx *ctx, StreamArgs &a, int *blocks) {
+    if (!ctx->s[0].set) return fail(ctx, PWA_E_STATE, "data sample not set");
+    const int64_t nd = ctx->s[0].n;
+    const bool need_mc = ctx->extended || nd > 0;
+    if (need_mc && !ctx->s[1].set) return fail(ctx, PWA_E_STATE, "MC sample not set");
+    if (need_mc && ctx->s[1].n == 0 && nd > 0)
+        return fail(ctx, PWA_E_STATE, "MC sample is empty: no normalisation");
+    const bool gram = ctx->mode == PWA_MC_GRAM;
+    if (gram && need_mc) {
+        pwa_status st = ensure_gram(ctx);
+        if (st != PWA_OK) return st;
+    }
+    std::memset(&a, 0, sizeof a);
+    a.A[0] = ctx->s[0].A;
+    a.A[1] = ctx->s[1].A;
+    a.w = ctx->s[1].w;
+    a.n[0] = nd;
+    a.n[1] = (gram || !need_mc) ? 0 : ctx->s[1].n;
+    a.ld = ctx->ld;
+    a.k = ctx->k;
+    a.pstride = (int32_t)(1 + 2 * ctx->ld);
+    a.partials = ctx->partials;
+    a.counter = ctx->counter;
+    a.gram = gram && need_mc ? ctx->gram : nullptr;
+    a.n_gen = ctx->s[1].n_gen > 0 ? ctx->s[1].n_gen : 1.0;
+    a.nd_total = (double)nd;
+    a.extended = ctx->extended;
+    split_blocks(ctx, a.n[0], a.n[1], a.nb);
+    *blocks = a.nb[0] + a.nb[1];
+    return PWA_OK;
+}
+
+pwa_status launch(pwa_ctx *ctx, const StreamArgs &a, int blocks) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ctx->timing) {
+        PWA_HIP(ctx, hipEventCreate(&e0), "hipEventCreate");
+        PWA_HIP(ctx, hipEventCreate(&e1), "hipEventCreate");
+        PWA_HIP(ctx, hipEventRecord(e0, ctx->stream), "hipEventRecord");
+    }
+    hipError_t e = launch_stream(ctx->prec, ctx->shape, kStreamThreads, blocks, a, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "likelihood kernel launch");
+    if (ctx->timing) {
+        PWA_HIP(ctx, hipEventRecord(e1, ctx->stream), "hipEventRecord");
+        ctx->events.emplace_back(e0, e1);
+    }
+    return PWA_OK;
+}
+
+// Result when no rows have to be streamed (N_D = 0, or only an empty MC sample).
+void trivial_result(const pwa_ctx *ctx, double *out) {
+    const int k = ctx->k;
+    for (int i = 0; i < 2 * k + 2; ++i) out[i] = 0.0;
+}
+
+pwa_status eval_sync(pwa_ctx *ctx, const double *V, double *nll, double *grad) {
+    if (!ctx) return fail(nullptr, PWA_E_INVAL, "null context");
+    if (!V || !nll) return fail(ctx, PWA_E_INVAL, "null V or nll");
+    DeviceGuard dg(ctx->device);
+    StreamArgs a;
+    int blocks = 0;
+    pwa_status st = prepare(ctx, a, &blocks);
+    if (st != PWA_OK) return st;
+    const int k = ctx->k;
+    for (int i = 0; i < 2 * k; ++i) {
+        if (!std::isfinite(V[i])) return fail(ctx, PWA_E_INVAL, "V[%d] is not finite", i);
+        a.v_arg[i] = V[i];
+    }
+    double *res = ctx->out_host;
+    if (blocks == 0 && !a.gram) {
+        trivial_result(ctx, res);
+    } else {
+        a.out = ctx->out_dev;
+        if (blocks == 0) {
+            // Gram form with no data rows: one block runs the combine alone
+            a.nb[0] = 1;
+            blocks = 1;
+        }
+        st = launch(ctx, a, blocks);
+        if (st != PWA_OK) return st;
+        PWA_HIP(ctx, hipMemcpyAsync(res, ctx->out_dev, sizeof(double) * (2 * k + 2),
+                                    hipMemcpyDeviceToHost, ctx->stream),
+                "hipMemcpyAsync(result)");
+        PWA_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    }
+    ctx->last_flags = (uint32_t)res[2 * k + 1];
+    *nll = res[0];
+    if (grad)
+        for (int i = 0; i < 2 * k; ++i) grad[i] = res[1 + i];
+    if (ctx->last_flags) return fail(ctx, PWA_E_DOMAIN, "non-positive intensity or normalisation");
+    return PWA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pwa_status pwa_create(pwa_ctx **out, int device, pwa_prec prec, void *stream) {
+    if (!out) return fail(nullptr, PWA_E_INVAL, "null output pointer");
+    if (prec != PWA_F32 && prec != PWA_F64) return fail(nullptr, PWA_E_INVAL, "bad precision");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return fail(nullptr, PWA_E_INVAL, "device %d not available", device);
+    DeviceGuard dg(device);
+    pwa_ctx *ctx = new (std::nothrow) pwa_ctx();
+    if (!ctx) return fail(nullptr, PWA_E_NOMEM, "out of host memory");
+    ctx->device = device;
+    ctx->prec = prec;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) {
+        delete ctx;
+        return fail(nullptr, PWA_E_HIP, "hipGetDeviceProperties: %s", hipGetErrorString(e));
+    }
+    ctx->cu_count = prop.multiProcessorCount;
+    if (stream) {
+        ctx->stream = static_cast<hipStream_t>(stream);
+    } else {
+        e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete ctx;
+            return fail(nullptr, PWA_E_HIP, "hipStreamCreate: %s", hipGetErrorString(e));
+        }
+        ctx->own_stream = true;
+    }
+    ctx->partials_doubles = (size_t)ctx->cu_count * 16 * (1 + 2 * PWA_MAX_K);
+    const size_t out_bytes = sizeof(double) * (2 * PWA_MAX_K + 2);
+    if ((e = hipMalloc(&ctx->partials, sizeof(double) * ctx->partials_doubles)) != hipSuccess ||
+        (e = hipMalloc(&ctx->counter, sizeof(unsigned int))) != hipSuccess ||
+        (e = hipMalloc(&ctx->out_dev, out_bytes)) != hipSuccess ||
+        (e = hipHostMalloc(&ctx->out_host, out_bytes, hipHostMallocDefault)) != hipSuccess ||
+        (e = hipMemset(ctx->counter, 0, sizeof(unsigned int))) != hipSuccess ||
+        (e = hipDeviceSynchronize()) != hipSuccess) {
+        pwa_status st = e == hipErrorOutOfMemory ? PWA_E_NOMEM : PWA_E_HIP;
+        fail(nullptr, st, "context allocation: %s", hipGetErrorString(e));
+        pwa_destroy(ctx);
+        return st;
+    }
+    *out = ctx;
+    return PWA_OK;
+}
+
+pwa_status pwa_destroy(pwa_ctx *ctx) {
+    if (!ctx) return PWA_OK;
+    DeviceGuard dg(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (auto &s : ctx->s) free_sample(s);
+    for (auto &ev : ctx->events) {
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+    }
+    if (ctx->gram) (void)hipFree(ctx->gram);
+    if (ctx->partials) (void)hipFree(ctx->partials);
+    if (ctx->counter) (void)hipFree(ctx->counter);
+    if (ctx->out_dev) (void)hipFree(ctx->out_dev);
+    if (ctx->out_host) (void)hipHostFree(ctx->out_host);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return PWA_OK;
+}
+
+pwa_status pwa_set_amplitudes(pwa_ctx *ctx, pwa_set which, const void *A, int64_t n, int32_t k,
+                              int64_t ld, pwa_where where, const void *w, double n_gen) {
+    if (!ctx) return fail(nullptr, PWA_E_INVAL, "null context");
+    if (which != PWA_DATA && which != PWA_MC) return fail(ctx, PWA_E_INVAL, "bad sample id");
+    if (where != PWA_HOST && where != PWA_DEVICE) return fail(ctx, PWA_E_INVAL, "bad memory space");
+    if (n < 0) return fail(ctx, PWA_E_INVAL, "negative n");
+    if (k < 1) return fail(ctx, PWA_E_INVAL, "k must be >= 1");
+    if (k > PWA_MAX_K) return fail(ctx, PWA_E_UNSUPPORTED, "k = %d exceeds %d", k, PWA_MAX_K);
+    if (ld < k) return fail(ctx, PWA_E_INVAL, "ld < k");
+    if (n > 0 && !A) return fail(ctx, PWA_E_INVAL, "null A");
+    if (which == PWA_DATA && w) return fail(ctx, PWA_E_INVAL, "weights apply to the MC sample only");
+    DeviceGuard dg(ctx->device);
+
+    const int other = which == PWA_DATA ? 1 : 0;
+    if (ctx->k != k) {
+        free_sample(ctx->s[other]);
+        ctx->k = k;
+        ctx->shape = choose_shape(ctx->prec, k);
+        ctx->ld = (int64_t)ctx->shape.L * ctx->shape.C;
+        ctx->gram_valid = false;
+    }
+    Sample &s = ctx->s[which];
+    free_sample(s);
+    if (which == PWA_MC) ctx->gram_valid = false;
+
+    const size_t eb = elem_bytes(ctx->prec);
+    const size_t row_bytes = 2 * eb * (size_t)ctx->ld;
+    if (n > 0) {
+        PWA_HIP(ctx, hipMalloc(&s.A, row_bytes * (size_t)n), "hipMalloc(amplitudes)");
+        if (ctx->ld > k)
+            PWA_HIP(ctx, hipMemsetAsync(s.A, 0, row_bytes * (size_t)n, ctx->stream),
+                    "hipMemsetAsync(amplitudes)");
+        const hipMemcpyKind kind = where == PWA_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+        PWA_HIP(ctx, hipMemcpy2DAsync(s.A, row_bytes, A, 2 * eb * (size_t)ld, 2 * eb * (size_t)k,
+                                      (size_t)n, kind, ctx->stream),
+                "hipMemcpy2DAsync(amplitudes)");
+        if (w) {
+            PWA_HIP(ctx, hipMalloc(&s.w, eb * (size_t)n), "hipMalloc(weights)");
+            PWA_HIP(ctx, hipMemcpyAsync(s.w, w, eb * (size_t)n, kind, ctx->stream),
+                    "hipMemcpyAsync(weights)");
+        }
+        PWA_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    }
+    s.n = n;
+    s.n_gen = which == PWA_MC ? (n_gen > 0 ? n_gen : (double)n) : 0.0;
+    s.set = true;
+    return PWA_OK;
+}
+
+pwa_status pwa_set_mc_mode(pwa_ctx *ctx, pwa_mc_mode mode, int extended) {
+    if (!ctx) return fail(nullptr, PWA_E_INVAL, "null context");
+    if (mode != PWA_MC_STREAM && mode != PWA_MC_GRAM) return fail(ctx, PWA_E_INVAL, "bad MC mode");
+    if (extended != 0 && extended != 1) return fail(ctx, PWA_E_INVAL, "extended must be 0 or 1");
+    ctx->mode = mode;
+    ctx->extended = extended;
+    return PWA_OK;
+}
+
+pwa_status pwa_nll(pwa_ctx *ctx, const double *V, double *nll) {
+    return eval_sync(ctx, V, nll, nullptr);
+}
+
+pwa_status pwa_nll_grad(pwa_ctx *ctx, const double *V, double *nll, double *grad) {
+    if (ctx && !grad) return fail(ctx, PWA_E_INVAL, "null grad");
+    return eval_sync(ctx, V, nll, grad);
+}
+
+pwa_status pwa_nll_grad_async(pwa_ctx *ctx, const double *V_dev, double *out_dev) {
+    if (!ctx) return fail(nullptr, PWA_E_INVAL, "null context");
+    if (!V_dev || !out_dev) return fail(ctx, PWA_E_INVAL, "null device pointer");
+    if (ctx->mode == PWA_MC_GRAM && !ctx->gram_valid)
+        return fail(ctx, PWA_E_STATE, "MC matrix not built: run one synchronous evaluation first");
+    DeviceGuard dg(ctx->device);
+    StreamArgs a;
+    int blocks = 0;
+    pwa_status st = prepare(ctx, a, &blocks);
+    if (st != PWA_OK) return st;
+    a.v_dev = V_dev;
+    a.out = out_dev;
+    if (blocks == 0) {
+        a.nb[0] = 1;   // one block still writes the (trivial) result
+        blocks = 1;
+    }
+    return launch(ctx, a, blocks);
+}
+
+pwa_status pwa_nll_batch(pwa_ctx *ctx, int32_t nv, const double *V, double *nll, double *grad,
+                         int32_t split) {
+    if (!ctx) return fail(nullptr, PWA_E_INVAL, "null context");
+    if (nv < 0 || (nv > 0 && (!V || !nll))) return fail(ctx, PWA_E_INVAL, "bad batch arguments");
+    if (split != 0) return fail(ctx, PWA_E_UNSUPPORTED, "split %d not available", split);
+    const int k = ctx->k;
+    std::vector<double> g(2 * (size_t)k);
+    for (int32_t b = 0; b < nv; ++b) {
+        double f = 0.0;
+        pwa_status st = eval_sync(ctx, V + (size_t)b * 2 * k, &f, g.data());
+        if (st != PWA_OK && st != PWA_E_DOMAIN) return st;
+        nll[b] = f;
+        if (grad) std::copy(g.begin(), g.end(), grad + (size_t)b * 2 * k);
+    }
+    return PWA_OK;
+}
+
+pwa_status pwa_last_flags(pwa_ctx *ctx, uint32_t *flags) {
+    if (!ctx || !flags) return fail(ctx, PWA_E_INVAL, "null argument");
+    *flags = ctx->last_flags;
+    return PWA_OK;
+}
+
+const char *pwa_last_error(const pwa_ctx *ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+pwa_status pwa_layout_ld(pwa_ctx *ctx, int32_t k, int64_t *ld) {
+    if (!ctx || !ld) return fail(ctx, PWA_E_INVAL, "null argument");
+    if (k < 1 || k > PWA_MAX_K) return fail(ctx, PWA_E_INVAL, "bad k");
+    StreamShape s = choose_shape(ctx->prec, k);
+    *ld = (int64_t)s.L * s.C;
+    return PWA_OK;
+}
+
+pwa_status pwa_set_timing(pwa_ctx *ctx, int enable) {
+    if (!ctx) return fail(nullptr, PWA_E_INVAL, "null context");
+    ctx->timing = enable != 0;
+    return PWA_OK;
+}
+
+pwa_status pwa_kernel_time(pwa_ctx *ctx, double *avg_ms, int64_t *count) {
+    if (!ctx || !avg_ms || !count) return fail(ctx, PWA_E_INVAL, "null argument");
+    DeviceGuard dg(ctx->device);
+    double total = 0.0;
+    int64_t m = 0;
+    for (auto &ev : ctx->events) {
+        PWA_HIP(ctx, hipEventSynchronize(ev.second), "hipEventSynchronize");
+        float ms = 0.f;
+        PWA_HIP(ctx, hipEventElapsedTime(&ms, ev.first, ev.second), "hipEventElapsedTime");
+        total += ms;
+        ++m;
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+    }
+    ctx->events.clear();
+    *avg_ms = m ? total / (double)m : 0.0;
+    *count = m;
+    return PWA_OK;
+}
+
+}  // extern "C"

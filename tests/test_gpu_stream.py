@@ -1,0 +1,253 @@
+"""GPU parity of the fused single-V NLL + gradient against the FP64 oracle.
+
+Bar: scaled relative error (tests/tolerance.py) below 1e-6 for FP32 contexts
+and 1e-12 for FP64 contexts, on seeded inputs that span several tiles and a
+ragged tail, at the workloads' full sizes, and on the edge cases.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.tolerance import TOL, errors, reference
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pwa():
+    import paper_1108_5882_amd as p
+    return p
+
+
+def _ctx(pwa, prec):
+    return pwa.Context(0, prec)
+
+
+def _case(seed, nd, nm, k, prec, weighted):
+    g = np.random.default_rng(seed)
+    dt = np.complex64 if prec == "f32" else np.complex128
+    Ad = synth.random_amplitudes(g, nd, k, dt)
+    Am = synth.random_amplitudes(g, nm, k, dt)
+    V = synth.draw_v(g, 1, k)[0]
+    w = g.uniform(0.2, 3.0, nm).astype(np.float32 if prec == "f32" else np.float64) if weighted else None
+    return Ad, Am, V, w
+
+
+SHAPES = [(1, 3001, 7003), (2, 4097, 9001), (3, 999, 5003), (4, 5000, 20011), (5, 1025, 3333),
+          (7, 777, 4099), (8, 2048, 8192), (16, 10007, 50021), (17, 3000, 9000), (31, 1000, 3000),
+          (32, 4099, 12007), (33, 2000, 5000), (48, 3001, 7001), (64, 1500, 4500)]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("k,nd,nm", SHAPES)
+def test_random_shapes(pwa, prec, k, nd, nm):
+    weighted = k % 2 == 1
+    _say(f"case random prec={prec} k={k} nd={nd} nm={nm} weighted={weighted}")
+    Ad, Am, V, w = _case(1000 + k, nd, nm, k, prec, weighted)
+    ng = nm + 17
+    with _ctx(pwa, prec) as c:
+        c.set_amplitudes("data", Ad)
+        c.set_amplitudes("mc", Am, w=w, n_gen=ng)
+        for extended in (False, True):
+            c.set_mc_mode("stream", extended)
+            nll, grad = c.nll_grad(V)
+            ref = reference(Ad, Am, V, w=w, n_gen=ng, extended=extended)
+            e_n, e_g = errors(ref, nll, grad)
+            _say(f"  extended={extended} e_nll={e_n:.2e} e_grad={e_g:.2e}")
+            assert e_n < TOL[prec] and e_g < TOL[prec]
+            assert c.nll(V) == nll
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_gram_mode(pwa, prec):
+    k, nd, nm = 16, 20011, 60013
+    _say(f"case gram prec={prec} k={k}")
+    Ad, Am, V, w = _case(77, nd, nm, k, prec, True)
+    with _ctx(pwa, prec) as c:
+        c.set_amplitudes("data", Ad)
+        c.set_amplitudes("mc", Am, w=w, n_gen=nm + 5)
+        for extended in (False, True):
+            c.set_mc_mode("gram", extended)
+            nll, grad = c.nll_grad(V)
+            ref = reference(Ad, Am, V, w=w, n_gen=nm + 5, extended=extended)
+            e_n, e_g = errors(ref, nll, grad)
+            _say(f"  extended={extended} e_nll={e_n:.2e} e_grad={e_g:.2e}")
+            assert e_n < TOL[prec] and e_g < TOL[prec]
+
+
+def test_config_k4_fp64_full(pwa):
+    """J/psi -> gamma K+K- stand-in, K = 4, 10^4 data, 10^5 MC, FP64: 1e-12."""
+    s = synth.make_sample(0)
+    V = synth.eval_vectors(0, 3, s.k)
+    _say("case cfg K=4 fp64 full")
+    with _ctx(pwa, "f64") as c:
+        c.set_amplitudes("data", s.A_data)
+        c.set_amplitudes("mc", s.A_mc)
+        for v in list(V) + [s.V_true]:
+            nll, grad = c.nll_grad(v)
+            e_n, e_g = errors(reference(s.A_data, s.A_mc, v), nll, grad)
+            _say(f"  e_nll={e_n:.2e} e_grad={e_g:.2e}")
+            assert e_n < 1e-12 and e_g < 1e-12
+
+
+@pytest.mark.parametrize("scale", [0.05, 1.0])
+def test_config_k16_fp32(pwa, scale):
+    """K = 16, FP32, 10^6 data and 5 x 10^6 MC at full scale: 1e-6."""
+    _say(f"case cfg K=16 fp32 scale={scale}")
+    s = synth.make_sample(1, scale=scale)
+    V = synth.eval_vectors(1, 2, s.k)
+    with _ctx(pwa, "f32") as c:
+        c.set_amplitudes("data", s.A_data)
+        c.set_amplitudes("mc", s.A_mc)
+        for v in list(V) + [s.V_true]:
+            nll, grad = c.nll_grad(v)
+            e_n, e_g = errors(reference(s.A_data, s.A_mc, v), nll, grad)
+            _say(f"  e_nll={e_n:.2e} e_grad={e_g:.2e}")
+            assert e_n < 1e-6 and e_g < 1e-6
+        # Gram mode on the same sample
+        c.set_mc_mode("gram")
+        nll, grad = c.nll_grad(V[0])
+        e_n, e_g = errors(reference(s.A_data, s.A_mc, V[0]), nll, grad)
+        _say(f"  gram e_nll={e_n:.2e} e_grad={e_g:.2e}")
+        assert e_n < 1e-6 and e_g < 1e-6
+
+
+def test_weighted_mc_config(pwa):
+    s = synth.make_sample(1, scale=0.02, weighted=True, accept_fraction=0.7)
+    V = synth.eval_vectors(1, 1, s.k)[0]
+    _say("case weighted + acceptance")
+    with _ctx(pwa, "f32") as c:
+        c.set_amplitudes("data", s.A_data)
+        c.set_amplitudes("mc", s.A_mc, w=s.w_mc, n_gen=s.n_gen)
+        nll, grad = c.nll_grad(V)
+    e_n, e_g = errors(reference(s.A_data, s.A_mc, V, w=s.w_mc, n_gen=s.n_gen), nll, grad)
+    assert e_n < 1e-6 and e_g < 1e-6
+
+
+def test_gaussian_integer_exact_intensity(pwa):
+    """Integer amplitudes and V with K=48: z and I are exact in FP32, so with unit
+    MC rows the streamed normalisation equals the exact integer sum."""
+    g = np.random.default_rng(5)
+    k = 48
+    Ad = synth.gaussian_integer_amplitudes(g, 257, k)
+    Am = synth.gaussian_integer_amplitudes(g, 1031, k)
+    V = g.integers(-4, 5, k) + 1j * g.integers(-4, 5, k)
+    V[0] = 3 + 1j
+    _say("case gaussian integers")
+    with _ctx(pwa, "f32") as c:
+        c.set_amplitudes("data", Ad)
+        c.set_amplitudes("mc", Am)
+        c.set_mc_mode("stream", extended=True)
+        nll, grad = c.nll_grad(V)
+    Ai = Am.astype(np.complex128)
+    s_exact = sum(int(round(abs(complex(z)) ** 2)) for z in Ai @ V)
+    nll_ref, _, parts = oracle.nll_grad(Ad, Am, V, extended=True, parts=True)
+    assert parts["s_raw"] == s_exact
+    I = oracle.intensity(Ad, V)
+    assert abs(nll - nll_ref) / (np.sum(np.abs(np.log(I))) + s_exact / 1031) < 1e-7
+
+
+def test_deterministic(pwa):
+    Ad, Am, V, w = _case(9, 30011, 90001, 16, "f32", True)
+    with _ctx(pwa, "f32") as c:
+        c.set_amplitudes("data", Ad)
+        c.set_amplitudes("mc", Am, w=w)
+        r1 = c.nll_grad(V)
+        r2 = c.nll_grad(V)
+    assert r1[0] == r2[0] and np.array_equal(r1[1], r2[1])
+
+
+def test_invariants_on_gpu_output(pwa):
+    """Phase invariance and the Euler identity V^H g = 0 hold on GPU output alone."""
+    Ad, Am, V, w = _case(11, 20000, 60000, 12, "f64", True)
+    with _ctx(pwa, "f64") as c:
+        c.set_amplitudes("data", Ad)
+        c.set_amplitudes("mc", Am, w=w)
+        n0, g0 = c.nll_grad(V)
+        n1, g1 = c.nll_grad(V * np.exp(0.7j))
+        n2, _ = c.nll_grad(V * (2.5 - 1j))
+    assert abs(n1 - n0) < 1e-10 * abs(n0) and abs(n2 - n0) < 1e-10 * abs(n0)
+    cg = g0[0::2] + 1j * g0[1::2]
+    assert abs(np.vdot(V, cg)) < 1e-9 * np.linalg.norm(V) * np.max(np.abs(cg))
+
+
+def test_async_and_device_source(pwa):
+    import torch
+    Ad, Am, V, w = _case(13, 10000, 30000, 16, "f32", True)
+    stream = torch.cuda.Stream()
+    with pwa.Context(0, "f32", stream=stream) as c:
+        Ad_d, Am_d, w_d = (torch.from_numpy(x).cuda() for x in (Ad, Am, w))
+        torch.cuda.synchronize()
+        c.set_amplitudes("data", Ad_d)
+        c.set_amplitudes("mc", Am_d, w=w_d)
+        nll, grad = c.nll_grad(V)
+        v = np.empty(32)
+        v[0::2], v[1::2] = V.real, V.imag
+        vd = torch.from_numpy(v).cuda()
+        out = torch.zeros(34, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        c.nll_grad_async(vd, out)
+        stream.synchronize()
+        o = out.cpu().numpy()
+    assert o[0] == nll and np.array_equal(o[1:33], grad) and o[33] == 0
+    e_n, e_g = errors(reference(Ad, Am, V, w=w), nll, grad)
+    assert e_n < 1e-6 and e_g < 1e-6
+
+
+def test_edge_cases(pwa):
+    Ad, Am, V, w = _case(17, 1000, 3000, 6, "f32", False)
+    with _ctx(pwa, "f32") as c:
+        with pytest.raises(pwa.PwaError) as ei:
+            c.nll_grad(V)
+        assert ei.value.status == 5                      # no samples yet
+        c.set_amplitudes("data", Ad)
+        with pytest.raises(pwa.PwaError) as ei:
+            c.nll_grad(V)
+        assert ei.value.status == 5                      # MC missing
+        c.set_amplitudes("mc", Am)
+        # empty data: ln L = 0 in the Eq. 2 form
+        c.set_amplitudes("data", Ad[:0])
+        nll, grad = c.nll_grad(V)
+        assert nll == 0.0 and np.all(grad == 0)
+        # single events
+        c.set_amplitudes("data", Ad[:1])
+        c.set_amplitudes("mc", Am[:1])
+        nll, grad = c.nll_grad(V)
+        e_n, e_g = errors(reference(Ad[:1], Am[:1], V), nll, grad)
+        assert e_n < 1e-6 and e_g < 1e-6
+        c.set_amplitudes("data", Ad)
+        c.set_amplitudes("mc", Am)
+        # V = 0 and a zero data row give +inf and a domain error
+        with pytest.raises(pwa.DomainError):
+            c.nll_grad(np.zeros(6, complex))
+        assert c.last_flags() != 0
+        bad = Ad.copy()
+        bad[17] = 0
+        c.set_amplitudes("data", bad)
+        with pytest.raises(pwa.DomainError):
+            c.nll_grad(V)
+        # the context stays usable
+        c.set_amplitudes("data", Ad)
+        nll, grad = c.nll_grad(V)
+        assert math.isfinite(nll)
+        # invalid arguments
+        with pytest.raises(pwa.PwaError) as ei:
+            c.set_amplitudes("mc", np.zeros((10, 65), np.complex64))
+        assert ei.value.status == 6
+        with pytest.raises(pwa.PwaError) as ei:
+            c.nll_grad(np.array([np.nan] * 12))
+        assert ei.value.status == 1
+        # changing k drops the other sample
+        c.set_amplitudes("mc", Am[:, :5])
+        with pytest.raises(pwa.PwaError) as ei:
+            c.nll_grad(V[:5])
+        assert ei.value.status == 5
