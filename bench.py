@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 METRIC = "NLL+grad event-evals/s, batched vs single-V at 1e-6 rel err; %HBM / %MFMA peak"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_nll_stream_k16.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1108_5882_amd", "csrc", "nll_stream.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_1108_5882_amd", "csrc", "nll_stream_impl.hpp")
 
 
 def log(msg):
@@ -69,10 +69,13 @@ def cpu_baseline(sample, V, budget_s: float):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probe", action="store_true",
+                    help="for HBM counter runs: a few evaluations plus a plain device copy of the "
+                         "same byte count (the counter scale reference); prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the likelihood path has no multi-GPU mode "
@@ -97,9 +100,21 @@ def main():
     ctx = Context(0, "f32", stream=stream)
     ctx.set_amplitudes("data", s.A_data)
     ctx.set_amplitudes("mc", s.A_mc)
+    cfg, tune_ms = ctx.autotune(reps=5)
+    log(f"autotuned stream configuration {cfg}: {tune_ms * 1e3:.1f} us")
     for _ in range(args.warmup):
         ctx.nll_grad(V)
     torch.cuda.synchronize()
+    if args.probe:
+        nbytes = units * 8 * k
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+            ctx.nll_grad(V)
+        torch.cuda.synchronize()
+        log(f"probe: 5 evaluations and 5 copies of {nbytes} bytes")
+        return
 
     ctx.set_timing(True)
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -123,7 +138,10 @@ def main():
     traffic = stored_traffic(units)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "nll_stream_kernel<float, L=8, C=2>", "kernel_ms": k_ms,
+            "kernel": "nll_stream_kernel<float, L=%d, C=%d, U=%d>, %d blocks/CU"
+                      % (cfg["lanes_per_row"], cfg["complex_per_lane"], cfg["rows_per_stage"],
+                         cfg["blocks_per_cu"]),
+            "kernel_ms": k_ms,
             "alg_bytes_per_launch": alg_bytes}
 
     rec = {

@@ -28,10 +28,11 @@
  * 4, "Fits with complex parameters").  Equivalently grad = 2 (Re g, Im g) with
  * g the Wirtinger derivative dNLL/d conj(V).
  *
- * Precision: PWA_F32 keeps amplitudes in single precision and computes each
- * event's z, I, ln I and z/I in single precision, with every sum over events
- * in double precision (the paper's remark on precision in Section 2).  PWA_F64
- * is double precision throughout.
+ * Precision: PWA_F32 stores and streams the amplitudes in single precision;
+ * each event's z, I and z/I are formed in double precision from the exact
+ * single-precision values and ln I is taken in single precision; every sum
+ * over events is in double precision (the paper's remark on precision in
+ * Section 2).  PWA_F64 is double precision throughout.
  *
  * Errors: every call returns a pwa_status.  On an error nothing is written to
  * the caller's outputs, except PWA_E_DOMAIN, which writes NLL = +inf (and an
@@ -149,9 +150,44 @@ const char *pwa_last_error(const pwa_ctx *ctx);
 /* Row stride (complex elements) of the library's device layout for k waves. */
 pwa_status pwa_layout_ld(pwa_ctx *ctx, int32_t k, int64_t *ld);
 
-/* Kernel timing: average duration in ms of the last `count` single-V kernel
- * launches, measured with HIP events on the context's stream, when timing is
- * enabled with pwa_set_timing(ctx, 1).  Timing adds an event pair per call. */
+/* Launch configuration of the single-V streaming kernel (a tile shape and grid
+ * size; none of it changes results beyond summation order).
+ *   lanes_per_row     L: lanes that share one event row (power of two)
+ *   complex_per_lane  C: consecutive complex amplitudes per lane; L * C must
+ *                     equal the layout width pwa_layout_ld() gives for k
+ *   rows_per_stage    U: rows each lane group loads per pipeline stage
+ *   blocks_per_cu     grid blocks per compute unit, 1..16 (fewer when the
+ *                     rows need fewer) */
+typedef struct {
+    int32_t lanes_per_row;
+    int32_t complex_per_lane;
+    int32_t rows_per_stage;
+    int32_t blocks_per_cu;
+} pwa_stream_cfg;
+
+/* Current configuration (after set_amplitudes fixed k). Errors: PWA_E_INVAL, PWA_E_STATE. */
+pwa_status pwa_get_stream_cfg(pwa_ctx *ctx, pwa_stream_cfg *cfg);
+
+/* Use `cfg` for later evaluations.  PWA_E_UNSUPPORTED if this (L, C, U) is
+ * not compiled or does not match the layout width; PWA_E_INVAL for a bad
+ * blocks_per_cu. */
+pwa_status pwa_set_stream_cfg(pwa_ctx *ctx, const pwa_stream_cfg *cfg);
+
+/* Autotuner: times every compiled configuration of the current layout width
+ * (and blocks_per_cu in {2, 3, 4, 6, 8, 12, 16}) on the samples currently set,
+ * `reps` evaluations each (the pass over the rows and the combine of its
+ * block partials) after one warm-up, keeps the fastest in the context and
+ * in a per-process cache keyed by (device, precision, width, sample sizes),
+ * which later contexts of the same shape start from.  Writes the chosen
+ * configuration and its average kernel time (ms) if the pointers are non-NULL.
+ * Needs both samples set.  Errors: PWA_E_STATE, PWA_E_HIP. */
+pwa_status pwa_autotune(pwa_ctx *ctx, int32_t reps, pwa_stream_cfg *best, double *best_ms);
+
+/* Kernel timing: average duration in ms of the streaming kernel (the pass over
+ * the rows, without the small combine kernel that follows it) over the
+ * single-V evaluations since the last query, measured with HIP events on the
+ * context's stream while timing is enabled with pwa_set_timing(ctx, 1).
+ * Timing adds an event pair per call. */
 pwa_status pwa_set_timing(pwa_ctx *ctx, int enable);
 pwa_status pwa_kernel_time(pwa_ctx *ctx, double *avg_ms, int64_t *count);
 

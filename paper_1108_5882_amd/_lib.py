@@ -26,8 +26,18 @@ MAX_K = 64
 EXPORTS = [
     "pwa_create", "pwa_destroy", "pwa_set_amplitudes", "pwa_set_mc_mode", "pwa_nll",
     "pwa_nll_grad", "pwa_nll_grad_async", "pwa_nll_batch", "pwa_last_flags", "pwa_last_error",
-    "pwa_layout_ld", "pwa_set_timing", "pwa_kernel_time",
+    "pwa_layout_ld", "pwa_set_timing", "pwa_kernel_time", "pwa_get_stream_cfg",
+    "pwa_set_stream_cfg", "pwa_autotune",
 ]
+
+
+class StreamCfg(ctypes.Structure):
+    """pwa_stream_cfg: launch configuration of the single-V streaming kernel."""
+    _fields_ = [("lanes_per_row", ctypes.c_int32), ("complex_per_lane", ctypes.c_int32),
+                ("rows_per_stage", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class PwaError(RuntimeError):
@@ -87,6 +97,9 @@ def load(path: str = LIB_PATH):
         "pwa_layout_ld": [P, I32, ctypes.POINTER(I64)],
         "pwa_set_timing": [P, ctypes.c_int],
         "pwa_kernel_time": [P, ctypes.POINTER(D), ctypes.POINTER(I64)],
+        "pwa_get_stream_cfg": [P, ctypes.POINTER(StreamCfg)],
+        "pwa_set_stream_cfg": [P, ctypes.POINTER(StreamCfg)],
+        "pwa_autotune": [P, I32, ctypes.POINTER(StreamCfg), ctypes.POINTER(D)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -250,6 +263,23 @@ class Context:
 
     def set_timing(self, enable: bool):
         self._check(self.lib.pwa_set_timing(self.h, int(bool(enable))))
+
+    def stream_cfg(self) -> dict:
+        c = StreamCfg()
+        self._check(self.lib.pwa_get_stream_cfg(self.h, ctypes.byref(c)))
+        return c.as_dict()
+
+    def set_stream_cfg(self, lanes_per_row, complex_per_lane, rows_per_stage, blocks_per_cu):
+        c = StreamCfg(lanes_per_row, complex_per_lane, rows_per_stage, blocks_per_cu)
+        self._check(self.lib.pwa_set_stream_cfg(self.h, ctypes.byref(c)))
+
+    def autotune(self, reps: int = 5):
+        """Times every compiled configuration on the current samples; keeps the fastest.
+        Returns (configuration dict, average kernel ms)."""
+        c = StreamCfg()
+        ms = ctypes.c_double()
+        self._check(self.lib.pwa_autotune(self.h, int(reps), ctypes.byref(c), ctypes.byref(ms)))
+        return c.as_dict(), ms.value
 
     def kernel_time(self):
         """(average ms, count) of the single-V kernels launched since the last query."""

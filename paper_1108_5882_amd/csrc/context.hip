@@ -8,6 +8,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -27,6 +30,18 @@ struct Sample {
 
 thread_local std::string g_err;
 
+// Tuned configurations shared by the contexts of one process.
+struct TuneKey {
+    int device;
+    int prec;
+    int64_t ld, nd, nm;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(device, prec, ld, nd, nm) < std::tie(o.device, o.prec, o.ld, o.nd, o.nm);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, StreamCfg> g_tune_cache;
+
 }  // namespace
 
 struct pwa_ctx {
@@ -37,7 +52,8 @@ struct pwa_ctx {
     int cu_count = 0;
 
     int32_t k = 0;
-    StreamShape shape{0, 0};
+    StreamCfg cfg{0, 0, 0, 4};
+    bool cfg_tuned = false;
     int64_t ld = 0;
     Sample s[2];
 
@@ -46,12 +62,11 @@ struct pwa_ctx {
     double *gram = nullptr;          // k x k complex FP64 (1/N_gen folded)
     bool gram_valid = false;
 
-    int blocks_per_cu = 4;
     double *partials = nullptr;
     size_t partials_doubles = 0;
-    unsigned int *counter = nullptr;
     double *out_dev = nullptr;       // [nll, grad[2k], flags]
-    double *out_host = nullptr;      // pinned copy target
+    double *out_host = nullptr;      // mapped pinned host memory the combine writes to
+    double *out_host_dev = nullptr;  // device address of out_host
     uint32_t last_flags = 0;
 
     bool timing = false;
@@ -110,12 +125,12 @@ void free_sample(Sample &s) {
 // Grid for one evaluation: blocks per segment, at most what the rows need and
 // at most blocks_per_cu per compute unit overall, split in proportion to rows.
 void split_blocks(const pwa_ctx *ctx, int64_t n0, int64_t n1, int32_t nb[2]) {
-    const int rows_per_wave = stream_rows_per_wave(ctx->prec, ctx->shape);
+    const int rows_per_wave = stream_rows_per_wave(ctx->cfg);
     const int waves_per_block = kStreamThreads / 64;
     const int64_t rows_per_block = (int64_t)rows_per_wave * waves_per_block;
     int64_t need[2] = {(n0 + rows_per_block - 1) / rows_per_block,
                        (n1 + rows_per_block - 1) / rows_per_block};
-    const int64_t budget = (int64_t)ctx->cu_count * ctx->blocks_per_cu;
+    const int64_t budget = (int64_t)ctx->cu_count * ctx->cfg.blocks_per_cu;
     if (need[0] + need[1] <= budget) {
         nb[0] = (int32_t)need[0];
         nb[1] = (int32_t)need[1];
@@ -178,7 +193,6 @@ pwa_status prepare(pwa_ctx *ctx, StreamArgs &a, int *blocks) {
     a.k = ctx->k;
     a.pstride = (int32_t)(1 + 2 * ctx->ld);
     a.partials = ctx->partials;
-    a.counter = ctx->counter;
     a.gram = gram && need_mc ? ctx->gram : nullptr;
     a.n_gen = ctx->s[1].n_gen > 0 ? ctx->s[1].n_gen : 1.0;
     a.nd_total = (double)nd;
@@ -195,12 +209,14 @@ pwa_status launch(pwa_ctx *ctx, const StreamArgs &a, int blocks) {
         PWA_HIP(ctx, hipEventCreate(&e1), "hipEventCreate");
         PWA_HIP(ctx, hipEventRecord(e0, ctx->stream), "hipEventRecord");
     }
-    hipError_t e = launch_stream(ctx->prec, ctx->shape, kStreamThreads, blocks, a, ctx->stream);
+    hipError_t e = launch_stream(ctx->prec, ctx->cfg, blocks, a, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "likelihood kernel launch");
     if (ctx->timing) {
         PWA_HIP(ctx, hipEventRecord(e1, ctx->stream), "hipEventRecord");
         ctx->events.emplace_back(e0, e1);
     }
+    e = launch_combine(a, stream_log_scale(ctx->prec), ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "combine kernel launch");
     return PWA_OK;
 }
 
@@ -227,7 +243,8 @@ pwa_status eval_sync(pwa_ctx *ctx, const double *V, double *nll, double *grad) {
     if (blocks == 0 && !a.gram) {
         trivial_result(ctx, res);
     } else {
-        a.out = ctx->out_dev;
+        // the combine kernel writes the result straight into mapped host memory
+        a.out = ctx->out_host_dev;
         if (blocks == 0) {
             // Gram form with no data rows: one block runs the combine alone
             a.nb[0] = 1;
@@ -235,9 +252,6 @@ pwa_status eval_sync(pwa_ctx *ctx, const double *V, double *nll, double *grad) {
         }
         st = launch(ctx, a, blocks);
         if (st != PWA_OK) return st;
-        PWA_HIP(ctx, hipMemcpyAsync(res, ctx->out_dev, sizeof(double) * (2 * k + 2),
-                                    hipMemcpyDeviceToHost, ctx->stream),
-                "hipMemcpyAsync(result)");
         PWA_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
     }
     ctx->last_flags = (uint32_t)res[2 * k + 1];
@@ -280,13 +294,14 @@ pwa_status pwa_create(pwa_ctx **out, int device, pwa_prec prec, void *stream) {
         }
         ctx->own_stream = true;
     }
-    ctx->partials_doubles = (size_t)ctx->cu_count * 16 * (1 + 2 * PWA_MAX_K);
+    const size_t max_blocks = (size_t)ctx->cu_count * kMaxBlocksPerCu;
+    ctx->partials_doubles = max_blocks * (1 + 2 * PWA_MAX_K);
     const size_t out_bytes = sizeof(double) * (2 * PWA_MAX_K + 2);
     if ((e = hipMalloc(&ctx->partials, sizeof(double) * ctx->partials_doubles)) != hipSuccess ||
-        (e = hipMalloc(&ctx->counter, sizeof(unsigned int))) != hipSuccess ||
         (e = hipMalloc(&ctx->out_dev, out_bytes)) != hipSuccess ||
-        (e = hipHostMalloc(&ctx->out_host, out_bytes, hipHostMallocDefault)) != hipSuccess ||
-        (e = hipMemset(ctx->counter, 0, sizeof(unsigned int))) != hipSuccess ||
+        (e = hipHostMalloc(&ctx->out_host, out_bytes, hipHostMallocMapped | hipHostMallocCoherent)) !=
+            hipSuccess ||
+        (e = hipHostGetDevicePointer((void **)&ctx->out_host_dev, ctx->out_host, 0)) != hipSuccess ||
         (e = hipDeviceSynchronize()) != hipSuccess) {
         pwa_status st = e == hipErrorOutOfMemory ? PWA_E_NOMEM : PWA_E_HIP;
         fail(nullptr, st, "context allocation: %s", hipGetErrorString(e));
@@ -308,7 +323,6 @@ pwa_status pwa_destroy(pwa_ctx *ctx) {
     }
     if (ctx->gram) (void)hipFree(ctx->gram);
     if (ctx->partials) (void)hipFree(ctx->partials);
-    if (ctx->counter) (void)hipFree(ctx->counter);
     if (ctx->out_dev) (void)hipFree(ctx->out_dev);
     if (ctx->out_host) (void)hipHostFree(ctx->out_host);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -333,8 +347,9 @@ pwa_status pwa_set_amplitudes(pwa_ctx *ctx, pwa_set which, const void *A, int64_
     if (ctx->k != k) {
         free_sample(ctx->s[other]);
         ctx->k = k;
-        ctx->shape = choose_shape(ctx->prec, k);
-        ctx->ld = (int64_t)ctx->shape.L * ctx->shape.C;
+        ctx->ld = stream_layout_ld(ctx->prec, k);
+        ctx->cfg = stream_default_cfg(ctx->prec, (int)ctx->ld);
+        ctx->cfg_tuned = false;
         ctx->gram_valid = false;
     }
     Sample &s = ctx->s[which];
@@ -362,6 +377,15 @@ pwa_status pwa_set_amplitudes(pwa_ctx *ctx, pwa_set which, const void *A, int64_
     s.n = n;
     s.n_gen = which == PWA_MC ? (n_gen > 0 ? n_gen : (double)n) : 0.0;
     s.set = true;
+    if (ctx->s[0].set && ctx->s[1].set) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(TuneKey{ctx->device, (int)ctx->prec, ctx->ld, ctx->s[0].n,
+                                            ctx->s[1].n});
+        if (it != g_tune_cache.end()) {
+            ctx->cfg = it->second;
+            ctx->cfg_tuned = true;
+        }
+    }
     return PWA_OK;
 }
 
@@ -430,8 +454,98 @@ const char *pwa_last_error(const pwa_ctx *ctx) { return ctx ? ctx->err.c_str() :
 pwa_status pwa_layout_ld(pwa_ctx *ctx, int32_t k, int64_t *ld) {
     if (!ctx || !ld) return fail(ctx, PWA_E_INVAL, "null argument");
     if (k < 1 || k > PWA_MAX_K) return fail(ctx, PWA_E_INVAL, "bad k");
-    StreamShape s = choose_shape(ctx->prec, k);
-    *ld = (int64_t)s.L * s.C;
+    *ld = stream_layout_ld(ctx->prec, k);
+    return PWA_OK;
+}
+
+pwa_status pwa_get_stream_cfg(pwa_ctx *ctx, pwa_stream_cfg *cfg) {
+    if (!ctx || !cfg) return fail(ctx, PWA_E_INVAL, "null argument");
+    if (ctx->k == 0) return fail(ctx, PWA_E_STATE, "no sample set");
+    *cfg = pwa_stream_cfg{ctx->cfg.L, ctx->cfg.C, ctx->cfg.U, ctx->cfg.blocks_per_cu};
+    return PWA_OK;
+}
+
+pwa_status pwa_set_stream_cfg(pwa_ctx *ctx, const pwa_stream_cfg *cfg) {
+    if (!ctx || !cfg) return fail(ctx, PWA_E_INVAL, "null argument");
+    if (ctx->k == 0) return fail(ctx, PWA_E_STATE, "no sample set");
+    if (cfg->blocks_per_cu < 1 || cfg->blocks_per_cu > kMaxBlocksPerCu)
+        return fail(ctx, PWA_E_INVAL, "blocks_per_cu must be in 1..16");
+    StreamCfg c{cfg->lanes_per_row, cfg->complex_per_lane, cfg->rows_per_stage, cfg->blocks_per_cu};
+    if (!stream_cfg_available(ctx->prec, c) || (int64_t)c.L * c.C != ctx->ld)
+        return fail(ctx, PWA_E_UNSUPPORTED, "configuration (L=%d, C=%d, U=%d) not available for width %lld",
+                    c.L, c.C, c.U, (long long)ctx->ld);
+    ctx->cfg = c;
+    return PWA_OK;
+}
+
+pwa_status pwa_autotune(pwa_ctx *ctx, int32_t reps, pwa_stream_cfg *best, double *best_ms) {
+    if (!ctx) return fail(nullptr, PWA_E_INVAL, "null context");
+    if (!ctx->s[0].set || !ctx->s[1].set) return fail(ctx, PWA_E_STATE, "samples not set");
+    if (reps < 1) reps = 1;
+    DeviceGuard dg(ctx->device);
+    const StreamCfg saved = ctx->cfg;
+    const bool saved_timing = ctx->timing;
+    ctx->timing = false;
+    StreamArgs a;
+    int blocks = 0;
+    pwa_status st = prepare(ctx, a, &blocks);
+    if (st != PWA_OK) return st;
+    for (int i = 0; i < ctx->k; ++i) {      // any nonzero V: only the time matters
+        a.v_arg[2 * i] = 1.0 / (1.0 + i);
+        a.v_arg[2 * i + 1] = 0.25;
+    }
+    a.out = ctx->out_dev;
+    hipEvent_t e0, e1;
+    PWA_HIP(ctx, hipEventCreate(&e0), "hipEventCreate");
+    PWA_HIP(ctx, hipEventCreate(&e1), "hipEventCreate");
+    static const int kBpc[] = {2, 3, 4, 6, 8, 12, 16};
+    int nvar = 0;
+    const StreamCfg *vars = stream_variants(ctx->prec, &nvar);
+    StreamCfg best_cfg = saved;
+    double best_t = 1e30;
+    hipError_t err = hipSuccess;
+    for (int v = 0; v < nvar && err == hipSuccess; ++v) {
+        if ((int64_t)vars[v].L * vars[v].C != ctx->ld) continue;
+        for (int bpc : kBpc) {
+            ctx->cfg = StreamCfg{vars[v].L, vars[v].C, vars[v].U, bpc};
+            split_blocks(ctx, a.n[0], a.n[1], a.nb);
+            int nb = a.nb[0] + a.nb[1];
+            if (nb < 1) { a.nb[0] = 1; nb = 1; }
+            // time the pass over the rows together with the combine it needs
+            auto both = [&]() {
+                hipError_t e2 = launch_stream(ctx->prec, ctx->cfg, nb, a, ctx->stream);
+                return e2 != hipSuccess ? e2 : launch_combine(a, stream_log_scale(ctx->prec), ctx->stream);
+            };
+            if ((err = both()) != hipSuccess) break;
+            if ((err = hipEventRecord(e0, ctx->stream)) != hipSuccess) break;
+            for (int r = 0; r < reps && err == hipSuccess; ++r) err = both();
+            if (err != hipSuccess) break;
+            if ((err = hipEventRecord(e1, ctx->stream)) != hipSuccess) break;
+            if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
+            float ms = 0.f;
+            if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+            const double t = ms / reps;
+            if (t < best_t) {
+                best_t = t;
+                best_cfg = ctx->cfg;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->timing = saved_timing;
+    if (err != hipSuccess) {
+        ctx->cfg = saved;
+        return hip_fail(ctx, err, "autotune");
+    }
+    ctx->cfg = best_cfg;
+    ctx->cfg_tuned = true;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[TuneKey{ctx->device, (int)ctx->prec, ctx->ld, ctx->s[0].n, ctx->s[1].n}] = best_cfg;
+    }
+    if (best) *best = pwa_stream_cfg{best_cfg.L, best_cfg.C, best_cfg.U, best_cfg.blocks_per_cu};
+    if (best_ms) *best_ms = best_t;
     return PWA_OK;
 }
 

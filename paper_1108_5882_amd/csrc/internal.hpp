@@ -22,8 +22,7 @@ struct StreamArgs {
     int32_t k;                 // waves
     int32_t pstride;           // doubles per block partial (1 + 2 ld)
     const double *v_dev;       // V on the device (2k doubles) or nullptr
-    double *partials;          // [nb[0] + nb[1]][pstride]
-    unsigned int *counter;     // finished-block counter, zero between launches
+    double *partials;          // [pstride][nb[0] + nb[1]] block partials (column-major)
     double *out;               // [nll, grad[2k], flags]
     const double *gram;        // MC matrix (k x k complex FP64, 1/N_gen folded) or nullptr
     double n_gen;              // N_gen of the MC estimate (stream mode)
@@ -33,34 +32,46 @@ struct StreamArgs {
     double v_arg[2 * PWA_MAX_K];   // V by value when v_dev is null
 };
 
-// Tile shape of the streaming kernel: L lanes cooperate on one event row,
-// each lane holding C consecutive complex amplitudes (ld = L * C).
-struct StreamShape {
+// Launch configuration of the streaming kernel: L lanes cooperate on one
+// event row, each lane holding C consecutive complex amplitudes (the device
+// layout's row width is ld = L * C); each lane group takes U rows per pipeline
+// stage; the grid has blocks_per_cu blocks per compute unit (fewer if the
+// rows need fewer).
+struct StreamCfg {
     int L;
     int C;
+    int U;
+    int blocks_per_cu;
 };
 
-// Rows each lane group loads per loop iteration (enough independent loads in
-// flight per lane); host and device share it to size the grid.
-__host__ __device__ constexpr int stream_unroll(int bytes_per_lane_row) {
-    return bytes_per_lane_row >= 32 ? 2 : (bytes_per_lane_row >= 16 ? 4 : 8);
-}
-
-// Rows one wave covers per loop iteration.
-inline int stream_rows_per_wave(pwa_prec prec, StreamShape s) {
-    const int bytes = (prec == PWA_F32 ? 8 : 16) * s.C;
-    return (64 / s.L) * stream_unroll(bytes);
-}
-
 constexpr int kStreamThreads = 256;
+constexpr int kMaxBlocksPerCu = 16;
 
-// Chooses the shape for k waves in the given precision (smallest padded row,
-// then the preferred per-lane load width).
-StreamShape choose_shape(pwa_prec prec, int k);
+// Rows one wave covers per pipeline stage.
+inline int stream_rows_per_wave(const StreamCfg &c) { return (64 / c.L) * c.U; }
 
-// Launches the fused kernel with the given shape; returns hipSuccess or the launch error.
-hipError_t launch_stream(pwa_prec prec, StreamShape s, int threads, int blocks,
-                         const StreamArgs &args, hipStream_t stream);
+// Every (L, C, U) compiled for the precision (blocks_per_cu left 0).
+const StreamCfg *stream_variants(pwa_prec prec, int *count);
+
+// Row width of the device layout for k waves: the smallest L * C >= k.
+int stream_layout_ld(pwa_prec prec, int k);
+
+// Default configuration for a layout width (used until a tuned one is set).
+StreamCfg stream_default_cfg(pwa_prec prec, int ld);
+
+// True if (L, C, U) is compiled for the precision.
+bool stream_cfg_available(pwa_prec prec, const StreamCfg &c);
+
+// Adds the block partials in a fixed order and writes [nll, grad[2k], flags]
+// to args.out (one block).  log_scale converts the summed log term to ln.
+hipError_t launch_combine(const StreamArgs &args, double log_scale, hipStream_t stream);
+
+// Scale that turns the streaming kernel's summed log term into ln (log2 sums in FP32 contexts).
+double stream_log_scale(pwa_prec prec);
+
+// Launches the streaming kernel (block partials only); returns hipSuccess or the launch error.
+hipError_t launch_stream(pwa_prec prec, const StreamCfg &cfg, int blocks, const StreamArgs &args,
+                         hipStream_t stream);
 
 // Gram matrix of the MC rows (Eq. 3 bracket), FP64 result on the device.
 //   partials: device scratch of at least gram_partial_doubles(k, blocks) doubles.

@@ -251,3 +251,50 @@ def test_edge_cases(pwa):
         with pytest.raises(pwa.PwaError) as ei:
             c.nll_grad(V[:5])
         assert ei.value.status == 5
+
+
+def _configs(c):
+    """Every compiled stream configuration for the context's current layout width."""
+    out = []
+    for L in (1, 2, 4, 8, 16, 32):
+        for C in (1, 2, 3, 4, 8):
+            for U in (1, 2, 4, 8):
+                try:
+                    c.set_stream_cfg(L, C, U, 4)
+                except Exception:
+                    continue
+                out.append((L, C, U))
+    return out
+
+
+@pytest.mark.parametrize("prec,k", [("f32", 16), ("f32", 5), ("f32", 48), ("f64", 4), ("f64", 24)])
+def test_every_stream_config(pwa, prec, k):
+    """Parity holds for every compiled tile shape and several grid sizes."""
+    Ad, Am, V, w = _case(300 + k, 7001, 20011, k, prec, True)
+    ref = reference(Ad, Am, V, w=w)
+    with _ctx(pwa, prec) as c:
+        c.set_amplitudes("data", Ad)
+        c.set_amplitudes("mc", Am, w=w)
+        cfgs = _configs(c)
+        assert cfgs
+        for (L, C, U) in cfgs:
+            for bpc in (1, 3, 16):
+                _say(f"case cfg prec={prec} k={k} L={L} C={C} U={U} bpc={bpc}")
+                c.set_stream_cfg(L, C, U, bpc)
+                nll, grad = c.nll_grad(V)
+                e_n, e_g = errors(ref, nll, grad)
+                assert e_n < TOL[prec] and e_g < TOL[prec], (L, C, U, bpc, e_n, e_g)
+
+
+def test_autotune_keeps_parity(pwa):
+    s = synth.make_sample(1, scale=0.05)
+    V = synth.eval_vectors(1, 1, s.k)[0]
+    with _ctx(pwa, "f32") as c:
+        c.set_amplitudes("data", s.A_data)
+        c.set_amplitudes("mc", s.A_mc)
+        cfg, ms = c.autotune(reps=3)
+        _say(f"autotune: {cfg} {ms:.4f} ms")
+        assert c.stream_cfg() == cfg and ms > 0
+        nll, grad = c.nll_grad(V)
+    e_n, e_g = errors(reference(s.A_data, s.A_mc, V), nll, grad)
+    assert e_n < 1e-6 and e_g < 1e-6
