@@ -133,11 +133,18 @@ pwa_status pwa_nll_grad_async(pwa_ctx *ctx, const double *V_dev, double *out_dev
  *   nll    host, nv doubles
  *   grad   host, nv x 2k doubles, or NULL for NLL only
  *   split  arithmetic of the dense contraction:
- *            0  FP32 vector arithmetic (reference path of the batched call)
- *            2  two-term FP16 split of A, V and the adjoint weights on matrix
- *               cores (FP32 accumulation)
- *            3  three-term BF16 split on matrix cores
- * Errors as pwa_nll; PWA_E_UNSUPPORTED for an FP64 context with split != 0. */
+ *            0  one streaming pass per vector (the single-V kernel; any precision)
+ *            2  matrix cores, one pass over the rows for all vectors: the
+ *               coherent sums z = A W use two-term FP16 splits (hi + lo) of
+ *               the amplitudes (power-of-two scale per wave) and of V (power-
+ *               of-two scale per vector); the adjoint sums conj(A) u use
+ *               two-term BF16 splits of u and of the amplitudes; FP32
+ *               accumulation within a block of at most 4096 events, FP64 across
+ *               blocks.  FP32 contexts only.
+ * V may hold any number of vectors; the FP64 results land in host memory.
+ * Errors as pwa_nll (PWA_E_DOMAIN if some vector's NLL is +inf; every output
+ * is written); PWA_E_UNSUPPORTED for another split, or split 2 in an FP64
+ * context. */
 pwa_status pwa_nll_batch(pwa_ctx *ctx, int32_t nv, const double *V, double *nll,
                          double *grad, int32_t split);
 
@@ -190,6 +197,10 @@ pwa_status pwa_autotune(pwa_ctx *ctx, int32_t reps, pwa_stream_cfg *best, double
  * Timing adds an event pair per call. */
 pwa_status pwa_set_timing(pwa_ctx *ctx, int enable);
 pwa_status pwa_kernel_time(pwa_ctx *ctx, double *avg_ms, int64_t *count);
+
+/* Same for the matrix-core pass of pwa_nll_batch (split 2), without its
+ * per-vector combine kernel. */
+pwa_status pwa_batch_kernel_time(pwa_ctx *ctx, double *avg_ms, int64_t *count);
 
 #ifdef __cplusplus
 }

@@ -27,7 +27,7 @@ EXPORTS = [
     "pwa_create", "pwa_destroy", "pwa_set_amplitudes", "pwa_set_mc_mode", "pwa_nll",
     "pwa_nll_grad", "pwa_nll_grad_async", "pwa_nll_batch", "pwa_last_flags", "pwa_last_error",
     "pwa_layout_ld", "pwa_set_timing", "pwa_kernel_time", "pwa_get_stream_cfg",
-    "pwa_set_stream_cfg", "pwa_autotune",
+    "pwa_set_stream_cfg", "pwa_autotune", "pwa_batch_kernel_time",
 ]
 
 
@@ -97,6 +97,7 @@ def load(path: str = LIB_PATH):
         "pwa_layout_ld": [P, I32, ctypes.POINTER(I64)],
         "pwa_set_timing": [P, ctypes.c_int],
         "pwa_kernel_time": [P, ctypes.POINTER(D), ctypes.POINTER(I64)],
+        "pwa_batch_kernel_time": [P, ctypes.POINTER(D), ctypes.POINTER(I64)],
         "pwa_get_stream_cfg": [P, ctypes.POINTER(StreamCfg)],
         "pwa_set_stream_cfg": [P, ctypes.POINTER(StreamCfg)],
         "pwa_autotune": [P, I32, ctypes.POINTER(StreamCfg), ctypes.POINTER(D)],
@@ -238,13 +239,15 @@ class Context:
         self._check(self.lib.pwa_nll_grad_async(self.h, ctypes.c_void_p(V_dev.data_ptr()),
                                                 ctypes.c_void_p(out_dev.data_ptr())))
 
-    def nll_batch(self, Vs, grad: bool = True, split: int = 0):
+    def nll_batch(self, Vs, grad: bool = True, split: int = 2):
+        """NLL (and gradients) for the rows of Vs [nv, k] complex (or [nv, 2k] real).
+        split 2: matrix-core pass for all vectors; split 0: one streaming pass each."""
         Vs = np.asarray(Vs)
         if np.iscomplexobj(Vs):
             v = np.empty((Vs.shape[0], 2 * Vs.shape[1]))
             v[:, 0::2], v[:, 1::2] = Vs.real, Vs.imag
         else:
-            v = np.ascontiguousarray(Vs, dtype=np.float64)
+            v = np.ascontiguousarray(Vs, dtype=np.float64).reshape(Vs.shape[0], -1)
         nv = v.shape[0]
         nll = np.zeros(nv)
         g = np.zeros_like(v) if grad else None
@@ -282,8 +285,15 @@ class Context:
         return c.as_dict(), ms.value
 
     def kernel_time(self):
-        """(average ms, count) of the single-V kernels launched since the last query."""
+        """(average ms, count) of the single-V streaming kernels since the last query."""
         ms = ctypes.c_double()
         n = ctypes.c_int64()
         self._check(self.lib.pwa_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def batch_kernel_time(self):
+        """(average ms, count) of the matrix-core batched kernels since the last query."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._check(self.lib.pwa_batch_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value

@@ -1,0 +1,398 @@
+// Many production vectors at once on the matrix cores (Berger, Section 2:
+// repeated fits from many starting points; Eq. 1-3 for each vector).
+//
+// For nv vectors the per-event coherent sums of all vectors form a dense
+// contraction: with A_r the N x 2K real view of the amplitude rows
+// (re, im interleaved) and W the 2K x 2nv real matrix whose columns for V_b
+// are (Re V_b, -Im V_b) and (Im V_b, Re V_b) interleaved per wave,
+//     Z = A_r W            (Re z_ib, Im z_ib in columns 2b, 2b + 1).
+// The adjoint sums are a second contraction over events,
+//     P = U^T A_r,  U_ib = z_ib / I_ib (data) or w_i z_ib (MC),
+//     Re G_ba = P[ur_b, 2a] + P[ui_b, 2a+1],  Im G_ba = P[ui_b, 2a] - P[ur_b, 2a+1].
+// Both run on v_mfma_f32_16x16x32_* in one kernel per event tile; U never
+// leaves registers: the forward's output layout is the adjoint's A operand
+// once the adjoint's event order is permuted the same way in both operands.
+//
+// Arithmetic (split): the forward uses two-term FP16 splits (hi + lo) of the
+// amplitudes, scaled by a power of two per wave, and of W, scaled by a power
+// of two per column: products hi*hi + hi*lo + lo*hi, 22-bit operands.  The
+// adjoint uses two-term BF16 splits of U and of the amplitudes (BF16 keeps
+// FP32's range, so the unbounded z/I needs no scale): 3 products.  MFMA
+// accumulation is FP32 within a block; each block covers at most
+// kTilesPerBlock tiles of one sample and writes FP64 partials per vector,
+// which a second kernel adds in block order (FP64) before forming NLL and
+// gradient per vector.
+#include "internal.hpp"
+
+#include <cmath>
+
+namespace pwa {
+namespace {
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+
+constexpr int kTile = 32;          // events per tile (two 16-row MFMA tiles)
+constexpr int kWaves = 8;          // waves per block
+constexpr int kThreads = 64 * kWaves;
+
+__device__ __forceinline__ int dpp_xor1(int x) {
+    return __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, true);   // quad_perm [1,0,3,2]
+}
+__device__ __forceinline__ float xor1_f(float x) { return __int_as_float(dpp_xor1(__float_as_int(x))); }
+
+// Block b covers tiles [t0, t0 + kTilesPerBlock) of one segment for the
+// vectors of blockIdx.y; each wave takes VPW = 8 CT vectors (2 CT real
+// columns in CT column tiles: re and im of 16 vectors per tile pair).
+template <int KS, int CT>
+__global__ __launch_bounds__(kThreads) void nll_batch_kernel(BatchArgs p) {
+    constexpr int kVPerWave = 8 * CT;
+    constexpr int K2 = 32 * KS;                 // padded real width
+    constexpr int RS16 = K2 + 8;                // row stride (halfs) of the row-major FP16 planes
+    constexpr int RST = kTile + 4;              // row stride (bf16) of the transposed planes
+    __shared__ __attribute__((aligned(16))) _Float16 ah[kTile * RS16];
+    __shared__ __attribute__((aligned(16))) _Float16 al[kTile * RS16];
+    __shared__ __attribute__((aligned(16))) __bf16 bh[K2 * RST];
+    __shared__ __attribute__((aligned(16))) __bf16 bl[K2 * RST];
+    __shared__ float wts[kTile];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int q = lane >> 4, r16 = lane & 15;
+    const int seg = (int)blockIdx.x < p.nb[0] ? 0 : 1;
+    const int bseg = seg ? (int)blockIdx.x - p.nb[0] : (int)blockIdx.x;
+    const int64_t n = p.n[seg];
+    const float *A = p.A[seg];
+    const float *w = seg ? p.w : nullptr;
+    const int64_t tile0 = (int64_t)bseg * kTilesPerBlock;
+    const int64_t ntiles = (n + kTile - 1) / kTile;
+    const int64_t tile1 = tile0 + kTilesPerBlock < ntiles ? tile0 + kTilesPerBlock : ntiles;
+    const int vg = (int)blockIdx.y * kWaves + wave;          // this wave's vector group
+    const int v0 = vg * kVPerWave;
+
+    // forward weights of this wave's vectors, fragment order [hi/lo][ct][ks][lane]
+    h8 wh[CT][KS], wl[CT][KS];
+    {
+        const h8 *src = reinterpret_cast<const h8 *>(p.wfrag) + (int64_t)vg * 2 * CT * KS * 64;
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                wh[ct][ks] = src[((0 * CT + ct) * KS + ks) * 64 + lane];
+                wl[ct][ks] = src[((1 * CT + ct) * KS + ks) * 64 + lane];
+            }
+    }
+
+    // adjoint accumulators D[ct][rtile]: lane holds rows 4q+e (columns of U) x col r16 (real)
+    f4 D[CT][2 * KS];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int rt = 0; rt < 2 * KS; ++rt) D[ct][rt] = f4{0.f, 0.f, 0.f, 0.f};
+    double tsum[CT / 2];            // per lane: sum over its events for vectors 16g + r16
+#pragma unroll
+    for (int g = 0; g < CT / 2; ++g) tsum[g] = 0.0;
+
+    const int nreal = 2 * p.k;                      // real columns present in a row
+    for (int64_t t = tile0; t < tile1; ++t) {
+        // ---- stage the tile: FP16 (scaled) row-major planes and BF16 transposed planes
+        __syncthreads();
+        for (int c = tid; c < kTile * K2 / 2; c += kThreads) {
+            const int e = c / (K2 / 2), r = 2 * (c % (K2 / 2));
+            const int64_t row = t * kTile + e;
+            float x0 = 0.f, x1 = 0.f;
+            if (row < n && r < nreal) {
+                const float *src = A + 2 * (row * p.ld) + r;
+                x0 = src[0];
+                x1 = r + 1 < nreal ? src[1] : 0.f;
+            }
+            const float s0 = p.ascale[r], s1 = p.ascale[r + 1];
+            const float y0 = x0 * s0, y1 = x1 * s1;
+            const _Float16 h0 = (_Float16)y0, h1 = (_Float16)y1;
+            ah[e * RS16 + r] = h0;
+            ah[e * RS16 + r + 1] = h1;
+            al[e * RS16 + r] = (_Float16)(y0 - (float)h0);
+            al[e * RS16 + r + 1] = (_Float16)(y1 - (float)h1);
+            const __bf16 g0 = (__bf16)x0, g1 = (__bf16)x1;
+            bh[r * RST + e] = g0;
+            bh[(r + 1) * RST + e] = g1;
+            bl[r * RST + e] = (__bf16)(x0 - (float)g0);
+            bl[(r + 1) * RST + e] = (__bf16)(x1 - (float)g1);
+        }
+        if (tid < kTile) {
+            const int64_t row = t * kTile + tid;
+            wts[tid] = row < n ? (w ? w[row] : 1.f) : 0.f;
+        }
+        __syncthreads();
+        if (v0 >= p.nv) continue;        // wave without vectors (last group)
+
+        // ---- forward: Z[rt][ct] (rows: events 16 rt + 4q + e, column r16 of tile ct)
+        f4 Z[2][CT];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) Z[rt][ct] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt) {
+                const int off = (16 * rt + r16) * RS16 + 32 * ks + 8 * q;
+                const h8 a_h = *reinterpret_cast<const h8 *>(&ah[off]);
+                const h8 a_l = *reinterpret_cast<const h8 *>(&al[off]);
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct) {
+                    Z[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_h, wh[ct][ks], Z[rt][ct], 0, 0, 0);
+                    Z[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_h, wl[ct][ks], Z[rt][ct], 0, 0, 0);
+                    Z[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_l, wh[ct][ks], Z[rt][ct], 0, 0, 0);
+                }
+            }
+
+        // ---- epilogue: per (event, vector) I, log2 I or w I, and U = z/I or w z,
+        // split into BF16 hi/lo in the adjoint's operand order
+        b8 uh[CT], ul[CT];
+#pragma unroll
+        for (int g = 0; g < CT / 2; ++g) {
+            const bool vok = v0 + 16 * g + r16 < p.nv;
+            float ts = 0.f;
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int ev = 16 * rt + 4 * q + e;
+                    const bool ok = vok && t * kTile + ev < n;
+                    const float zr = Z[rt][2 * g][e], zi = Z[rt][2 * g + 1][e];
+                    const float I = fmaf(zr, zr, zi * zi);
+                    float ur, ui;
+                    if (seg == 0) {
+                        ts += ok ? __log2f(I) : 0.f;
+                        const float rI = ok ? __builtin_amdgcn_rcpf(I) : 0.f;
+                        ur = zr * rI;
+                        ui = zi * rI;
+                    } else {
+                        const float wv = ok ? wts[ev] : 0.f;
+                        ts = fmaf(wv, I, ts);
+                        ur = wv * zr;
+                        ui = wv * zi;
+                    }
+                    const int slot = 4 * rt + e;   // adjoint k order: events 4q+e, then 16+4q+e
+                    const __bf16 hr = (__bf16)ur, hi_ = (__bf16)ui;
+                    uh[2 * g][slot] = hr;
+                    uh[2 * g + 1][slot] = hi_;
+                    ul[2 * g][slot] = (__bf16)(ur - (float)hr);
+                    ul[2 * g + 1][slot] = (__bf16)(ui - (float)hi_);
+                }
+            tsum[g] += (double)ts;
+        }
+
+        // ---- adjoint: D[ct][rt] += U^T (16 columns x 32 events) . A (32 events x 16 reals)
+#pragma unroll
+        for (int rt = 0; rt < 2 * KS; ++rt) {
+            const int rr = 16 * rt + r16;
+            b8 b_h, b_l;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                b_h[e] = bh[rr * RST + 4 * q + e];
+                b_h[4 + e] = bh[rr * RST + 16 + 4 * q + e];
+                b_l[e] = bl[rr * RST + 4 * q + e];
+                b_l[4 + e] = bl[rr * RST + 16 + 4 * q + e];
+            }
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                D[ct][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uh[ct], b_h, D[ct][rt], 0, 0, 0);
+                D[ct][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uh[ct], b_l, D[ct][rt], 0, 0, 0);
+                D[ct][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ul[ct], b_h, D[ct][rt], 0, 0, 0);
+            }
+        }
+    }
+    if (v0 >= p.nv) return;
+
+    // ---- per-vector scalar sums: lanes r16, r16 + 16, r16 + 32, r16 + 48 share a vector
+#pragma unroll
+    for (int g = 0; g < CT / 2; ++g) {
+        tsum[g] += __shfl_xor(tsum[g], 16);
+        tsum[g] += __shfl_xor(tsum[g], 32);
+    }
+    // partial layout [v][block][1 + 2 ld]: [0] scalar, [1 + 2a + c] complex sums
+    const int pst = p.pstride;
+    const int nblk = p.nb[0] + p.nb[1];
+    if (q == 0) {
+#pragma unroll
+        for (int g = 0; g < CT / 2; ++g) {
+            const int v = v0 + 16 * g + r16;
+            if (v < p.nv) p.partials[((int64_t)v * nblk + blockIdx.x) * pst] = tsum[g];
+        }
+    }
+    // gradient sums: lane pairs (2a, 2a+1) in r16 hold the re and im real rows of wave a
+#pragma unroll
+    for (int g = 0; g < CT / 2; ++g)
+#pragma unroll
+        for (int rt = 0; rt < 2 * KS; ++rt)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float pr = D[2 * g][rt][e];       // P[ur_v, real r]
+                const float pi = D[2 * g + 1][rt][e];   // P[ui_v, real r]
+                const float pr_o = xor1_f(pr), pi_o = xor1_f(pi);   // the odd real row
+                const int v = v0 + 16 * g + 4 * q + e;
+                const int rr = 16 * rt + r16;
+                if ((r16 & 1) == 0 && v < p.nv && rr < nreal) {
+                    const int a = rr >> 1;
+                    double *dst = p.partials + ((int64_t)v * nblk + blockIdx.x) * pst + 1 + 2 * a;
+                    dst[0] = (double)pr + (double)pi_o;      // Re G = P[ur, 2a] + P[ui, 2a+1]
+                    dst[1] = (double)pi - (double)pr_o;      // Im G = P[ui, 2a] - P[ur, 2a+1]
+                }
+            }
+}
+
+// Per vector v (one block each): add the block partials of each segment in
+// block order, undo the per-vector scale t_v of the forward weights, and form
+// NLL and gradient (Eq. 2 or Eq. 3 form; streamed MC or the MC matrix).
+__global__ __launch_bounds__(256) void nll_batch_combine_kernel(BatchArgs p) {
+    __shared__ double tot[2][1 + 2 * PWA_MAX_K];
+    __shared__ double mv[2 * PWA_MAX_K];
+    __shared__ double s_c;
+    const int v = blockIdx.x, tid = threadIdx.x;
+    const int pst = p.pstride;
+    const int nblk = p.nb[0] + p.nb[1];
+    const int k = p.k;
+    const double *base = p.partials + (int64_t)v * nblk * pst;
+    for (int idx = tid; idx < 2 * pst; idx += 256) {
+        const int sg = idx / pst, cc = idx % pst;
+        const int b0 = sg ? p.nb[0] : 0, b1 = sg ? nblk : p.nb[0];
+        double s = 0.0;
+        for (int b = b0; b < b1; ++b) s += base[(int64_t)b * pst + cc];
+        tot[sg][cc] = s;
+    }
+    __syncthreads();
+    const double tv = p.vscale[v];
+    const double *V = p.V + (int64_t)v * 2 * k;
+    if (p.gram) {
+        for (int a = tid; a < k; a += 256) {
+            double r = 0.0, i = 0.0;
+            for (int b = 0; b < k; ++b) {
+                const double mr = p.gram[2 * (a * k + b)], mi = p.gram[2 * (a * k + b) + 1];
+                r += mr * V[2 * b] - mi * V[2 * b + 1];
+                i += mr * V[2 * b + 1] + mi * V[2 * b];
+            }
+            mv[2 * a] = r;
+            mv[2 * a + 1] = i;
+        }
+    }
+    __syncthreads();
+    double *out = p.out + (int64_t)v * (2 * k + 2);
+    if (tid == 0) {
+        const double nd = p.nd_total;
+        // Z = t_v z, so sum ln I = ln 2 sum log2 I' - 2 N_D ln t_v and sum w I = sum w I' / t_v^2
+        const double sum_log = tot[0][0] * 0.69314718055994530942 - 2.0 * nd * log(tv);
+        double S, c;
+        if (p.gram) {
+            double s = 0.0;
+            for (int a = 0; a < k; ++a) s += V[2 * a] * mv[2 * a] + V[2 * a + 1] * mv[2 * a + 1];
+            S = s;
+            c = p.extended ? 1.0 : nd / S;
+        } else {
+            const double s_raw = tot[1][0] / (tv * tv);
+            S = s_raw / p.n_gen;
+            c = p.extended ? 1.0 / p.n_gen : nd / s_raw;
+        }
+        double nll;
+        unsigned flags = 0;
+        if (!p.extended && nd == 0.0) {
+            nll = 0.0;
+            c = 0.0;
+        } else {
+            nll = p.extended ? -sum_log + S : -sum_log + nd * log(S);
+            if (!isfinite(nll) || (!p.extended && !(S > 0.0))) {
+                nll = INFINITY;
+                flags = 1;
+            }
+        }
+        out[0] = nll;
+        out[1 + 2 * k] = (double)flags;
+        s_c = c;
+    }
+    __syncthreads();
+    const double c = s_c;
+    const bool zero = !p.extended && p.nd_total == 0.0;
+    // data sums carry u = t_v Z'/I' (x t_v); MC sums carry w Z' = t_v w z (/ t_v)
+    for (int i = tid; i < 2 * k; i += 256) {
+        const double g = tot[0][1 + i] * tv;
+        const double h = p.gram ? mv[i] : tot[1][1 + i] / tv;
+        out[1 + i] = zero ? 0.0 : 2.0 * (-g + c * h);
+    }
+}
+
+// Largest |re| or |im| of each wave over a sample's rows (FP32), as float bits
+// in an atomicMax (non-negative floats order like their bit patterns).
+__global__ void amax_kernel(const float *A, int64_t n, int64_t ld, int k, unsigned *out) {
+    __shared__ unsigned sm[PWA_MAX_K];
+    for (int a = threadIdx.x; a < k; a += blockDim.x) sm[a] = 0u;
+    __syncthreads();
+    const int64_t total = n * (int64_t)k;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = i / k;
+        const int a = (int)(i % k);
+        const float *x = A + 2 * (row * ld + a);
+        const float m = fmaxf(fabsf(x[0]), fabsf(x[1]));
+        atomicMax(&sm[a], __float_as_uint(m));
+    }
+    __syncthreads();
+    for (int a = threadIdx.x; a < k; a += blockDim.x) atomicMax(&out[a], sm[a]);
+}
+
+}  // namespace
+
+size_t batch_partial_doubles(int64_t n0, int64_t n1, int nv, int k) {
+    const int64_t nb = batch_blocks(n0) + batch_blocks(n1);
+    return (size_t)nb * (size_t)nv * (size_t)(1 + 2 * k);
+}
+
+int64_t batch_blocks(int64_t n) {
+    const int64_t tiles = (n + kTile - 1) / kTile;
+    return (tiles + kTilesPerBlock - 1) / kTilesPerBlock;
+}
+
+int batch_ks(int k) { return (2 * k + 31) / 32; }
+
+int batch_ct(int k) { return batch_ks(k) <= 2 ? 4 : 2; }
+
+int batch_vectors_per_wave(int k) { return 8 * batch_ct(k); }
+
+int batch_vector_groups(int nv, int k) {
+    const int vpw = batch_vectors_per_wave(k);
+    return (nv + vpw - 1) / vpw;
+}
+
+hipError_t launch_amax(const float *A, int64_t n, int64_t ld, int k, unsigned *out,
+                       hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const int64_t blocks64 = (n * k + 255) / 256;
+    const int blocks = (int)(blocks64 < 4096 ? blocks64 : 4096);
+    hipLaunchKernelGGL(amax_kernel, dim3(blocks), dim3(256), 0, stream, A, n, ld, k, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchArgs &args, hipStream_t stream) {
+    const int nblk = args.nb[0] + args.nb[1];
+    if (nblk > 0) {
+        const int gy = (batch_vector_groups(args.nv, args.k) + kWaves - 1) / kWaves;
+        const dim3 grid(nblk, gy);
+        switch (batch_ks(args.k)) {
+            case 1: hipLaunchKernelGGL((nll_batch_kernel<1, 4>), grid, dim3(kThreads), 0, stream, args); break;
+            case 2: hipLaunchKernelGGL((nll_batch_kernel<2, 4>), grid, dim3(kThreads), 0, stream, args); break;
+            case 3: hipLaunchKernelGGL((nll_batch_kernel<3, 2>), grid, dim3(kThreads), 0, stream, args); break;
+            case 4: hipLaunchKernelGGL((nll_batch_kernel<4, 2>), grid, dim3(kThreads), 0, stream, args); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_batch_combine(const BatchArgs &args, hipStream_t stream) {
+    hipLaunchKernelGGL(nll_batch_combine_kernel, dim3(args.nv), dim3(256), 0, stream, args);
+    return hipGetLastError();
+}
+
+}  // namespace pwa

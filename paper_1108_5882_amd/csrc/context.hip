@@ -71,6 +71,15 @@ struct pwa_ctx {
 
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> batch_events;
+
+    // batched (many-V) path: per-wave FP16 scales of the amplitudes, device scratch
+    bool amax_valid = false;
+    std::vector<float> ascale;
+    void *b_wfrag = nullptr, *b_ascale = nullptr, *b_vscale = nullptr, *b_V = nullptr;
+    void *b_partials = nullptr, *b_out = nullptr;
+    size_t b_cap[6] = {0, 0, 0, 0, 0, 0};
+    unsigned *b_amax = nullptr;
 
     std::string err;
 };
@@ -262,6 +271,179 @@ pwa_status eval_sync(pwa_ctx *ctx, const double *V, double *nll, double *grad) {
     return PWA_OK;
 }
 
+// Grows a device scratch buffer to at least `bytes`.
+pwa_status grow(pwa_ctx *ctx, void **buf, size_t *cap, size_t bytes, const char *what) {
+    if (*cap >= bytes) return PWA_OK;
+    if (*buf) (void)hipFree(*buf);
+    *buf = nullptr;
+    *cap = 0;
+    PWA_HIP(ctx, hipMalloc(buf, bytes), what);
+    *cap = bytes;
+    return PWA_OK;
+}
+
+// Power of two p with m * p in [2^13, 2^14) (1 for m = 0): FP16 operand scale.
+double fp16_scale(double m) {
+    if (!(m > 0.0)) return 1.0;
+    const int e = (int)std::floor(std::log2(m));
+    return std::ldexp(1.0, 13 - e);
+}
+
+// Per-wave power-of-two FP16 scales of the amplitudes from the largest
+// |re| or |im| of each wave over both samples.
+pwa_status ensure_amax(pwa_ctx *ctx) {
+    if (ctx->amax_valid) return PWA_OK;
+    const int k = ctx->k;
+    if (!ctx->b_amax) PWA_HIP(ctx, hipMalloc(&ctx->b_amax, sizeof(unsigned) * PWA_MAX_K), "hipMalloc(amax)");
+    PWA_HIP(ctx, hipMemsetAsync(ctx->b_amax, 0, sizeof(unsigned) * PWA_MAX_K, ctx->stream), "hipMemsetAsync");
+    for (int sg = 0; sg < 2; ++sg) {
+        const Sample &sm = ctx->s[sg];
+        if (!sm.set || sm.n == 0) continue;
+        hipError_t e = launch_amax(static_cast<const float *>(sm.A), sm.n, ctx->ld, k, ctx->b_amax, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "amax kernel");
+    }
+    unsigned bits[PWA_MAX_K];
+    PWA_HIP(ctx, hipMemcpyAsync(bits, ctx->b_amax, sizeof(unsigned) * k, hipMemcpyDeviceToHost, ctx->stream),
+            "hipMemcpyAsync(amax)");
+    PWA_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    const int k2 = 32 * batch_ks(k);
+    ctx->ascale.assign(k2, 1.0f);
+    for (int a = 0; a < k; ++a) {
+        float m;
+        std::memcpy(&m, &bits[a], sizeof m);
+        const float sc = (float)fp16_scale((double)m);
+        ctx->ascale[2 * a] = ctx->ascale[2 * a + 1] = sc;
+    }
+    ctx->amax_valid = true;
+    return PWA_OK;
+}
+
+pwa_status batch_mfma(pwa_ctx *ctx, int32_t nv, const double *V, double *nll, double *grad) {
+    DeviceGuard dg(ctx->device);
+    const int k = ctx->k;
+    if (!ctx->s[0].set) return fail(ctx, PWA_E_STATE, "data sample not set");
+    const int64_t nd = ctx->s[0].n;
+    const bool need_mc = ctx->extended || nd > 0;
+    if (need_mc && !ctx->s[1].set) return fail(ctx, PWA_E_STATE, "MC sample not set");
+    if (need_mc && ctx->s[1].n == 0 && nd > 0)
+        return fail(ctx, PWA_E_STATE, "MC sample is empty: no normalisation");
+    const bool gram = ctx->mode == PWA_MC_GRAM && need_mc;
+    if (gram) {
+        pwa_status st = ensure_gram(ctx);
+        if (st != PWA_OK) return st;
+    }
+    pwa_status st = ensure_amax(ctx);
+    if (st != PWA_OK) return st;
+
+    const int ks = batch_ks(k), k2 = 32 * ks, ctn = batch_ct(k), vpw = batch_vectors_per_wave(k);
+    const int ngroups = batch_vector_groups(nv, k);
+    const int gy = (ngroups + kBatchWaves - 1) / kBatchWaves;   // blocks cover kBatchWaves groups
+    const int gpad = gy * kBatchWaves;
+    // forward weights W' = W t_v / s_a, FP16 hi + lo, in MFMA B-operand fragment order
+    std::vector<_Float16> wf((size_t)gpad * 2 * ctn * ks * 64 * 8, (_Float16)0.0f);
+    std::vector<double> vscale(nv);
+    for (int v = 0; v < nv; ++v) {
+        const double *vv = V + (size_t)v * 2 * k;
+        double m = 0.0;
+        for (int a = 0; a < k; ++a)
+            m = std::max(m, std::max(std::fabs(vv[2 * a]), std::fabs(vv[2 * a + 1])) / ctx->ascale[2 * a]);
+        vscale[v] = fp16_scale(m);
+    }
+    for (int grp = 0; grp < ngroups; ++grp)
+        for (int ct = 0; ct < ctn; ++ct)
+            for (int kk = 0; kk < ks; ++kk)
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int e = 0; e < 8; ++e) {
+                        const int r = 32 * kk + 8 * (lane >> 4) + e;      // real row
+                        const int v = grp * vpw + 16 * (ct >> 1) + (lane & 15);
+                        double x = 0.0;
+                        if (v < nv && r < 2 * k) {
+                            const double *vv = V + (size_t)v * 2 * k;
+                            const int a = r >> 1;
+                            const double vr = vv[2 * a], vi = vv[2 * a + 1];
+                            // column re: (Re V, -Im V) on rows (2a, 2a+1); column im: (Im V, Re V)
+                            const double wv = (ct & 1) == 0 ? ((r & 1) == 0 ? vr : -vi)
+                                                            : ((r & 1) == 0 ? vi : vr);
+                            x = wv * vscale[v] / ctx->ascale[r];
+                        }
+                        const _Float16 hi = (_Float16)(float)x;
+                        const _Float16 lo = (_Float16)(float)(x - (double)(float)hi);
+                        const size_t base = ((((size_t)grp * 2 + 0) * ctn + ct) * ks + kk) * 64 + lane;
+                        const size_t basel = ((((size_t)grp * 2 + 1) * ctn + ct) * ks + kk) * 64 + lane;
+                        wf[base * 8 + e] = hi;
+                        wf[basel * 8 + e] = lo;
+                    }
+
+    BatchArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.A[0] = static_cast<const float *>(ctx->s[0].A);
+    a.A[1] = static_cast<const float *>(ctx->s[1].A);
+    a.w = static_cast<const float *>(ctx->s[1].w);
+    a.n[0] = nd;
+    a.n[1] = (gram || !need_mc) ? 0 : ctx->s[1].n;
+    a.ld = ctx->ld;
+    a.k = k;
+    a.nv = nv;
+    a.nb[0] = (int32_t)batch_blocks(a.n[0]);
+    a.nb[1] = (int32_t)batch_blocks(a.n[1]);
+    a.pstride = 1 + 2 * k;
+    a.extended = ctx->extended;
+    a.n_gen = ctx->s[1].n_gen > 0 ? ctx->s[1].n_gen : 1.0;
+    a.nd_total = (double)nd;
+    a.gram = gram ? ctx->gram : nullptr;
+    const size_t out_doubles = (size_t)nv * (2 * k + 2);
+    if ((st = grow(ctx, &ctx->b_wfrag, &ctx->b_cap[0], wf.size() * sizeof(_Float16), "hipMalloc(weights)")) ||
+        (st = grow(ctx, &ctx->b_ascale, &ctx->b_cap[1], sizeof(float) * k2, "hipMalloc(scales)")) ||
+        (st = grow(ctx, &ctx->b_vscale, &ctx->b_cap[2], sizeof(double) * nv, "hipMalloc(scales)")) ||
+        (st = grow(ctx, &ctx->b_V, &ctx->b_cap[3], sizeof(double) * 2 * k * (size_t)nv, "hipMalloc(V)")) ||
+        (st = grow(ctx, &ctx->b_partials, &ctx->b_cap[4],
+                   sizeof(double) * std::max<size_t>(1, batch_partial_doubles(a.n[0], a.n[1], nv, k)),
+                   "hipMalloc(partials)")) ||
+        (st = grow(ctx, &ctx->b_out, &ctx->b_cap[5], sizeof(double) * out_doubles, "hipMalloc(out)")))
+        return st;
+    PWA_HIP(ctx, hipMemcpyAsync(ctx->b_wfrag, wf.data(), wf.size() * sizeof(_Float16), hipMemcpyHostToDevice,
+                                ctx->stream), "hipMemcpyAsync(weights)");
+    PWA_HIP(ctx, hipMemcpyAsync(ctx->b_ascale, ctx->ascale.data(), sizeof(float) * k2, hipMemcpyHostToDevice,
+                                ctx->stream), "hipMemcpyAsync(scales)");
+    PWA_HIP(ctx, hipMemcpyAsync(ctx->b_vscale, vscale.data(), sizeof(double) * nv, hipMemcpyHostToDevice,
+                                ctx->stream), "hipMemcpyAsync(scales)");
+    PWA_HIP(ctx, hipMemcpyAsync(ctx->b_V, V, sizeof(double) * 2 * k * (size_t)nv, hipMemcpyHostToDevice,
+                                ctx->stream), "hipMemcpyAsync(V)");
+    a.wfrag = ctx->b_wfrag;
+    a.ascale = static_cast<const float *>(ctx->b_ascale);
+    a.vscale = static_cast<const double *>(ctx->b_vscale);
+    a.V = static_cast<const double *>(ctx->b_V);
+    a.partials = static_cast<double *>(ctx->b_partials);
+    a.out = static_cast<double *>(ctx->b_out);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ctx->timing) {
+        PWA_HIP(ctx, hipEventCreate(&e0), "hipEventCreate");
+        PWA_HIP(ctx, hipEventCreate(&e1), "hipEventCreate");
+        PWA_HIP(ctx, hipEventRecord(e0, ctx->stream), "hipEventRecord");
+    }
+    hipError_t e = launch_batch(a, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "batched kernel launch");
+    if (ctx->timing) {
+        PWA_HIP(ctx, hipEventRecord(e1, ctx->stream), "hipEventRecord");
+        ctx->batch_events.emplace_back(e0, e1);
+    }
+    e = launch_batch_combine(a, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "batched combine launch");
+    std::vector<double> out(out_doubles);
+    PWA_HIP(ctx, hipMemcpyAsync(out.data(), ctx->b_out, sizeof(double) * out_doubles, hipMemcpyDeviceToHost,
+                                ctx->stream), "hipMemcpyAsync(result)");
+    PWA_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    bool domain = false;
+    for (int v = 0; v < nv; ++v) {
+        const double *o = out.data() + (size_t)v * (2 * k + 2);
+        nll[v] = o[0];
+        domain |= o[2 * k + 1] != 0.0;
+        if (grad) std::copy(o + 1, o + 1 + 2 * k, grad + (size_t)v * 2 * k);
+    }
+    ctx->last_flags = domain ? 1u : 0u;
+    return domain ? fail(ctx, PWA_E_DOMAIN, "non-positive intensity or normalisation") : PWA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -317,11 +499,15 @@ pwa_status pwa_destroy(pwa_ctx *ctx) {
     DeviceGuard dg(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     for (auto &s : ctx->s) free_sample(s);
-    for (auto &ev : ctx->events) {
-        (void)hipEventDestroy(ev.first);
-        (void)hipEventDestroy(ev.second);
-    }
+    for (auto *list : {&ctx->events, &ctx->batch_events})
+        for (auto &ev : *list) {
+            (void)hipEventDestroy(ev.first);
+            (void)hipEventDestroy(ev.second);
+        }
     if (ctx->gram) (void)hipFree(ctx->gram);
+    for (void *b : {ctx->b_wfrag, ctx->b_ascale, ctx->b_vscale, ctx->b_V, ctx->b_partials, ctx->b_out,
+                    (void *)ctx->b_amax})
+        if (b) (void)hipFree(b);
     if (ctx->partials) (void)hipFree(ctx->partials);
     if (ctx->out_dev) (void)hipFree(ctx->out_dev);
     if (ctx->out_host) (void)hipHostFree(ctx->out_host);
@@ -355,6 +541,7 @@ pwa_status pwa_set_amplitudes(pwa_ctx *ctx, pwa_set which, const void *A, int64_
     Sample &s = ctx->s[which];
     free_sample(s);
     if (which == PWA_MC) ctx->gram_valid = false;
+    ctx->amax_valid = false;
 
     const size_t eb = elem_bytes(ctx->prec);
     const size_t row_bytes = 2 * eb * (size_t)ctx->ld;
@@ -430,17 +617,27 @@ pwa_status pwa_nll_batch(pwa_ctx *ctx, int32_t nv, const double *V, double *nll,
                          int32_t split) {
     if (!ctx) return fail(nullptr, PWA_E_INVAL, "null context");
     if (nv < 0 || (nv > 0 && (!V || !nll))) return fail(ctx, PWA_E_INVAL, "bad batch arguments");
-    if (split != 0) return fail(ctx, PWA_E_UNSUPPORTED, "split %d not available", split);
+    if (split != 0 && split != 2) return fail(ctx, PWA_E_UNSUPPORTED, "split %d not available", split);
+    if (split == 2 && ctx->prec != PWA_F32)
+        return fail(ctx, PWA_E_UNSUPPORTED, "the matrix-core path needs an FP32 context");
+    for (int64_t i = 0; i < (int64_t)nv * 2 * ctx->k; ++i)
+        if (!std::isfinite(V[i])) return fail(ctx, PWA_E_INVAL, "V is not finite");
+    if (nv == 0) return PWA_OK;
     const int k = ctx->k;
-    std::vector<double> g(2 * (size_t)k);
-    for (int32_t b = 0; b < nv; ++b) {
-        double f = 0.0;
-        pwa_status st = eval_sync(ctx, V + (size_t)b * 2 * k, &f, g.data());
-        if (st != PWA_OK && st != PWA_E_DOMAIN) return st;
-        nll[b] = f;
-        if (grad) std::copy(g.begin(), g.end(), grad + (size_t)b * 2 * k);
+    if (split == 0) {
+        std::vector<double> g(2 * (size_t)k);
+        bool domain = false;
+        for (int32_t b = 0; b < nv; ++b) {
+            double f = 0.0;
+            pwa_status st = eval_sync(ctx, V + (size_t)b * 2 * k, &f, g.data());
+            if (st != PWA_OK && st != PWA_E_DOMAIN) return st;
+            domain |= st == PWA_E_DOMAIN;
+            nll[b] = f;
+            if (grad) std::copy(g.begin(), g.end(), grad + (size_t)b * 2 * k);
+        }
+        return domain ? fail(ctx, PWA_E_DOMAIN, "non-positive intensity or normalisation") : PWA_OK;
     }
-    return PWA_OK;
+    return batch_mfma(ctx, nv, V, nll, grad);
 }
 
 pwa_status pwa_last_flags(pwa_ctx *ctx, uint32_t *flags) {
@@ -555,12 +752,14 @@ pwa_status pwa_set_timing(pwa_ctx *ctx, int enable) {
     return PWA_OK;
 }
 
-pwa_status pwa_kernel_time(pwa_ctx *ctx, double *avg_ms, int64_t *count) {
-    if (!ctx || !avg_ms || !count) return fail(ctx, PWA_E_INVAL, "null argument");
+namespace {
+pwa_status drain_events(pwa_ctx *ctx, std::vector<std::pair<hipEvent_t, hipEvent_t>> &list,
+                        double *avg_ms, int64_t *count) {
+    if (!avg_ms || !count) return fail(ctx, PWA_E_INVAL, "null argument");
     DeviceGuard dg(ctx->device);
     double total = 0.0;
     int64_t m = 0;
-    for (auto &ev : ctx->events) {
+    for (auto &ev : list) {
         PWA_HIP(ctx, hipEventSynchronize(ev.second), "hipEventSynchronize");
         float ms = 0.f;
         PWA_HIP(ctx, hipEventElapsedTime(&ms, ev.first, ev.second), "hipEventElapsedTime");
@@ -569,10 +768,21 @@ pwa_status pwa_kernel_time(pwa_ctx *ctx, double *avg_ms, int64_t *count) {
         (void)hipEventDestroy(ev.first);
         (void)hipEventDestroy(ev.second);
     }
-    ctx->events.clear();
+    list.clear();
     *avg_ms = m ? total / (double)m : 0.0;
     *count = m;
     return PWA_OK;
+}
+}  // namespace
+
+pwa_status pwa_kernel_time(pwa_ctx *ctx, double *avg_ms, int64_t *count) {
+    if (!ctx) return fail(nullptr, PWA_E_INVAL, "null context");
+    return drain_events(ctx, ctx->events, avg_ms, count);
+}
+
+pwa_status pwa_batch_kernel_time(pwa_ctx *ctx, double *avg_ms, int64_t *count) {
+    if (!ctx) return fail(nullptr, PWA_E_INVAL, "null context");
+    return drain_events(ctx, ctx->batch_events, avg_ms, count);
 }
 
 }  // extern "C"

@@ -73,6 +73,43 @@ double stream_log_scale(pwa_prec prec);
 hipError_t launch_stream(pwa_prec prec, const StreamCfg &cfg, int blocks, const StreamArgs &args,
                          hipStream_t stream);
 
+// Arguments of the batched (many-V) kernels.
+struct BatchArgs {
+    const float *A[2];         // FP32 device rows (data, MC), ld complex each
+    const float *w;            // MC weights or nullptr
+    int64_t n[2];
+    int64_t ld;
+    int32_t k;
+    int32_t nv;                // number of production vectors
+    int32_t nb[2];             // blocks per segment (kTilesPerBlock tiles each)
+    int32_t pstride;           // doubles per (vector, block) partial: 1 + 2k
+    int32_t extended;
+    const void *wfrag;         // FP16 forward weights in MFMA fragment order
+    const float *ascale;       // power-of-two scale per real column (32 * ks entries)
+    const double *vscale;      // power-of-two scale of each vector's weights
+    const double *V;           // nv x 2k production vectors (FP64)
+    const double *gram;        // MC matrix or nullptr
+    double n_gen;
+    double nd_total;
+    double *partials;          // [nv][blocks][pstride]
+    double *out;               // [nv][2k + 2]: nll, grad, flags
+};
+
+constexpr int kTilesPerBlock = 128;
+constexpr int kBatchWaves = 8;       // waves (vector groups) per block of the batched kernel
+
+int64_t batch_blocks(int64_t n);
+int batch_ks(int k);
+int batch_ct(int k);                 // column tiles per wave (4 for k <= 32, else 2)
+int batch_vectors_per_wave(int k);   // 8 * batch_ct(k)
+int batch_vector_groups(int nv, int k);
+size_t batch_partial_doubles(int64_t n0, int64_t n1, int nv, int k);
+hipError_t launch_amax(const float *A, int64_t n, int64_t ld, int k, unsigned *out,
+                       hipStream_t stream);
+// The matrix-core pass (block partials per vector), then the per-vector combine.
+hipError_t launch_batch(const BatchArgs &args, hipStream_t stream);
+hipError_t launch_batch_combine(const BatchArgs &args, hipStream_t stream);
+
 // Gram matrix of the MC rows (Eq. 3 bracket), FP64 result on the device.
 //   partials: device scratch of at least gram_partial_doubles(k, blocks) doubles.
 hipError_t launch_gram(pwa_prec prec, const void *A, const void *w, int64_t n, int64_t ld, int k,
