@@ -202,6 +202,64 @@ pwa_status pwa_kernel_time(pwa_ctx *ctx, double *avg_ms, int64_t *count);
  * per-vector combine kernel. */
 pwa_status pwa_batch_kernel_time(pwa_ctx *ctx, double *avg_ms, int64_t *count);
 
+/* ------------------------------------------------------------------------
+ * Many independent fits (Section 2: fits are repeated from many starting
+ * points and with many models).  Every fit has its own samples and its own
+ * production vector; one minimiser iteration of all fits is one persistent
+ * evaluation launch over the rows of every fit (uneven sizes balanced by a
+ * work-item queue), a per-fit combine, and one L-BFGS update per fit on the
+ * device, captured in a HIP graph and replayed per step.  FP32 amplitudes, the
+ * Eq. 2 form, streamed MC.
+ * ------------------------------------------------------------------------ */
+typedef struct pwa_multi pwa_multi;
+
+/* One fit: host arrays, FP32 interleaved complex rows of stride ld (>= k). */
+typedef struct {
+    const float *A_data;
+    int64_t n_data;
+    const float *A_mc;
+    int64_t n_mc;          /* > 0 when n_data > 0 */
+    const float *w_mc;     /* MC weights or NULL */
+    double n_gen;          /* <= 0: n_mc */
+    int32_t k;             /* 1..48 */
+    int64_t ld;
+    const double *V0;      /* 2k start vector */
+} pwa_fit_desc;
+
+/* Copy every fit's samples to the device and set each minimiser at its V0.
+ * `stream`: hipStream_t or NULL (owned).  Errors: PWA_E_INVAL, PWA_E_NOMEM,
+ * PWA_E_HIP, PWA_E_UNSUPPORTED (k > 48). */
+pwa_status pwa_multi_create(pwa_multi **out, int device, int32_t nfits, const pwa_fit_desc *fits,
+                            void *stream);
+pwa_status pwa_multi_destroy(pwa_multi *m);
+
+/* Evaluate every fit at V (host; the fits' 2k vectors concatenated) in one
+ * persistent launch: nll[nfits], grad (concatenated, may be NULL).  Overwrites
+ * the minimisers' trial points; call pwa_multi_reset before stepping again.
+ * PWA_E_DOMAIN if some fit's NLL is +inf (all outputs written). */
+pwa_status pwa_multi_eval(pwa_multi *m, const double *V, double *nll, double *grad);
+
+/* Restart every minimiser at V0 (concatenated). */
+pwa_status pwa_multi_reset(pwa_multi *m, const double *V0);
+
+/* Replay `steps` minimiser iterations (the captured graph).  Each replay
+ * evaluates every fit's trial point and advances its L-BFGS state (Armijo
+ * backtracking; history 8).  avg_ms (optional): HIP-event time per replay. */
+pwa_status pwa_multi_step(pwa_multi *m, int32_t steps, double *avg_ms);
+
+/* Current accepted points (concatenated), NLL values, status (0 running,
+ * 1 converged, 2 step underflow) and accepted iterations per fit; any pointer
+ * may be NULL. */
+pwa_status pwa_multi_get(pwa_multi *m, double *V, double *nll, int32_t *status, int32_t *iters);
+
+/* Autotuner of the persistent launch: times the evaluation of all fits for
+ * work items of 64 KB .. 1 MB of rows and 1 .. 8 blocks per compute unit,
+ * `reps` launches each, keeps the fastest (and rebuilds the graph). */
+pwa_status pwa_multi_autotune(pwa_multi *m, int32_t reps, int64_t *item_bytes, int32_t *blocks_per_cu,
+                              double *best_ms);
+
+const char *pwa_multi_last_error(const pwa_multi *m);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,7 +28,16 @@ EXPORTS = [
     "pwa_nll_grad", "pwa_nll_grad_async", "pwa_nll_batch", "pwa_last_flags", "pwa_last_error",
     "pwa_layout_ld", "pwa_set_timing", "pwa_kernel_time", "pwa_get_stream_cfg",
     "pwa_set_stream_cfg", "pwa_autotune", "pwa_batch_kernel_time",
+    "pwa_multi_create", "pwa_multi_destroy", "pwa_multi_eval", "pwa_multi_reset", "pwa_multi_step",
+    "pwa_multi_get", "pwa_multi_autotune", "pwa_multi_last_error",
 ]
+
+
+class FitDesc(ctypes.Structure):
+    """pwa_fit_desc: one fit of a multi-fit set (host arrays)."""
+    _fields_ = [("A_data", ctypes.c_void_p), ("n_data", ctypes.c_int64), ("A_mc", ctypes.c_void_p),
+                ("n_mc", ctypes.c_int64), ("w_mc", ctypes.c_void_p), ("n_gen", ctypes.c_double),
+                ("k", ctypes.c_int32), ("ld", ctypes.c_int64), ("V0", ctypes.c_void_p)]
 
 
 class StreamCfg(ctypes.Structure):
@@ -101,6 +110,13 @@ def load(path: str = LIB_PATH):
         "pwa_get_stream_cfg": [P, ctypes.POINTER(StreamCfg)],
         "pwa_set_stream_cfg": [P, ctypes.POINTER(StreamCfg)],
         "pwa_autotune": [P, I32, ctypes.POINTER(StreamCfg), ctypes.POINTER(D)],
+        "pwa_multi_create": [ctypes.POINTER(P), ctypes.c_int, I32, ctypes.POINTER(FitDesc), P],
+        "pwa_multi_destroy": [P],
+        "pwa_multi_eval": [P, P, P, P],
+        "pwa_multi_reset": [P, P],
+        "pwa_multi_step": [P, I32, ctypes.POINTER(D)],
+        "pwa_multi_get": [P, P, P, P, P],
+        "pwa_multi_autotune": [P, I32, ctypes.POINTER(I64), ctypes.POINTER(I32), ctypes.POINTER(D)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -108,6 +124,8 @@ def load(path: str = LIB_PATH):
         f.restype = st
     lib.pwa_last_error.argtypes = [P]
     lib.pwa_last_error.restype = ctypes.c_char_p
+    lib.pwa_multi_last_error.argtypes = [P]
+    lib.pwa_multi_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib
 
@@ -297,3 +315,111 @@ class Context:
         n = ctypes.c_int64()
         self._check(self.lib.pwa_batch_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+class MultiFit:
+    """Many independent fits minimised together on one GPU (pwa_multi).
+
+    samples: list of (A_data [n_d, k] complex64, A_mc [n_m, k] complex64, w_mc or None,
+    n_gen or None); V0: list of complex [k] start vectors.
+    """
+
+    def __init__(self, samples, V0, device: int = 0, stream=None):
+        self.lib = load()
+        self.ks = []
+        self._keep = []
+        descs = (FitDesc * len(samples))()
+        for f, ((Ad, Am, w, ng), v0) in enumerate(zip(samples, V0)):
+            Ad = np.ascontiguousarray(Ad, dtype=np.complex64)
+            Am = np.ascontiguousarray(Am, dtype=np.complex64)
+            k = Ad.shape[1]
+            wa = None if w is None else np.ascontiguousarray(w, dtype=np.float32)
+            v = np.empty(2 * k)
+            v0 = np.asarray(v0)
+            v[0::2], v[1::2] = v0.real, v0.imag
+            self._keep += [Ad, Am, wa, v]
+            self.ks.append(k)
+            descs[f] = FitDesc(Ad.ctypes.data, Ad.shape[0], Am.ctypes.data, Am.shape[0],
+                               None if wa is None else wa.ctypes.data, float(ng or 0.0), k, k,
+                               v.ctypes.data)
+        h = ctypes.c_void_p()
+        s = _stream_handle(stream)
+        st = self.lib.pwa_multi_create(ctypes.byref(h), device, len(samples), descs,
+                                       None if s is None else ctypes.c_void_p(s))
+        self._keep = []
+        self.h = h
+        self._check(st, None)
+        self.n = 2 * sum(self.ks)
+
+    def _check(self, status: int, h=-1):
+        if status == OK:
+            return
+        msg = self.lib.pwa_multi_last_error(self.h if h == -1 else h)
+        msg = msg.decode() if msg else ""
+        raise (DomainError if status == E_DOMAIN else PwaError)(status, msg)
+
+    def _concat(self, Vs):
+        out = np.empty(self.n)
+        off = 0
+        for k, v in zip(self.ks, Vs):
+            v = np.asarray(v)
+            out[off:off + 2 * k:2], out[off + 1:off + 2 * k:2] = v.real, v.imag
+            off += 2 * k
+        return out
+
+    def _split(self, flat):
+        res, off = [], 0
+        for k in self.ks:
+            res.append(flat[off:off + 2 * k:2] + 1j * flat[off + 1:off + 2 * k:2])
+            off += 2 * k
+        return res
+
+    def eval(self, Vs):
+        """(nll[nfits], list of real gradients) at the complex vectors Vs."""
+        v = self._concat(Vs)
+        nll = np.zeros(len(self.ks))
+        g = np.zeros(self.n)
+        self._check(self.lib.pwa_multi_eval(self.h, _ptr(v), _ptr(nll), _ptr(g)))
+        grads, off = [], 0
+        for k in self.ks:
+            grads.append(g[off:off + 2 * k].copy())
+            off += 2 * k
+        return nll, grads
+
+    def reset(self, Vs):
+        v = self._concat(Vs)
+        self._check(self.lib.pwa_multi_reset(self.h, _ptr(v)))
+
+    def step(self, steps: int = 1) -> float:
+        """Replay `steps` minimiser iterations; returns the average ms per iteration."""
+        ms = ctypes.c_double()
+        self._check(self.lib.pwa_multi_step(self.h, int(steps), ctypes.byref(ms)))
+        return ms.value
+
+    def get(self):
+        """(list of complex V, nll[nfits], status[nfits], iters[nfits])."""
+        v = np.zeros(self.n)
+        nll = np.zeros(len(self.ks))
+        st = np.zeros(len(self.ks), dtype=np.int32)
+        it = np.zeros(len(self.ks), dtype=np.int32)
+        self._check(self.lib.pwa_multi_get(self.h, _ptr(v), _ptr(nll), _ptr(st), _ptr(it)))
+        return self._split(v), nll, st, it
+
+    def autotune(self, reps: int = 3):
+        b = ctypes.c_int64()
+        c = ctypes.c_int32()
+        ms = ctypes.c_double()
+        self._check(self.lib.pwa_multi_autotune(self.h, int(reps), ctypes.byref(b), ctypes.byref(c),
+                                                ctypes.byref(ms)))
+        return {"item_bytes": b.value, "blocks_per_cu": c.value}, ms.value
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.pwa_multi_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

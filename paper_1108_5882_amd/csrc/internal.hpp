@@ -110,6 +110,56 @@ hipError_t launch_amax(const float *A, int64_t n, int64_t ld, int k, unsigned *o
 hipError_t launch_batch(const BatchArgs &args, hipStream_t stream);
 hipError_t launch_batch_combine(const BatchArgs &args, hipStream_t stream);
 
+// ---------------------------------------------------------------- multi-fit
+constexpr int kMultiMaxLd = 48;                   // widest row of the multi-fit kernel
+constexpr int kMultiSlot = 1 + 2 * kMultiMaxLd;   // doubles per item partial
+constexpr int kMultiOut = 2 * kMultiMaxLd + 2;    // doubles per fit result
+constexpr int kLbfgsMaxHist = 16;
+constexpr int kLbfgsMaxN = 2 * kMultiMaxLd;
+
+struct MultiFit {
+    const float *A_data;       // device rows, ld complex each, zero padded
+    const float *A_mc;
+    const float *w_mc;         // MC weights or nullptr
+    int64_t n_data, n_mc;
+    int64_t ld;                // row width: one of multi_layout_ld's widths
+    int32_t k;
+    int32_t item_data0, item_data1, item_mc0, item_mc1;   // item ranges of the two samples
+    int32_t pad_;
+    double n_gen;
+    const double *V;           // trial vector (2k doubles) the evaluation reads
+};
+
+struct MultiItem {
+    int32_t fit;
+    int32_t seg;               // 0 data, 1 MC
+    int64_t t0, t1;            // tile range within the sample
+};
+
+struct MultiArgs {
+    const MultiFit *fits;
+    const MultiItem *items;
+    int32_t n_fits, n_items;
+    unsigned *item_counter;    // zero before a launch; the combine resets it
+    double *partials;          // [items][kMultiSlot]
+    double *out;               // [fits][kMultiOut]: nll, grad[2k], flags
+};
+
+// L-BFGS state of one fit (device memory).
+struct LbfgsState {
+    double x[kLbfgsMaxN], g[kLbfgsMaxN], xt[kLbfgsMaxN], d[kLbfgsMaxN];
+    double S[kLbfgsMaxHist][kLbfgsMaxN], Y[kLbfgsMaxHist][kLbfgsMaxN], rho[kLbfgsMaxHist];
+    double f, alpha, gtd;
+    int32_t head, count, phase, iter, status, nbacktrack;
+};
+
+int64_t multi_layout_ld(int k);              // -1 if k is too large
+bool multi_ld_supported(int64_t ld);
+int multi_rows_per_tile(int64_t ld);         // rows one wave covers per tile
+hipError_t launch_multi_eval(const MultiArgs &args, int blocks, hipStream_t stream);
+hipError_t launch_lbfgs(const MultiFit *fits, const double *out, LbfgsState *states, int nfits,
+                        int m, double c1, double ftol, hipStream_t stream);
+
 // Gram matrix of the MC rows (Eq. 3 bracket), FP64 result on the device.
 //   partials: device scratch of at least gram_partial_doubles(k, blocks) doubles.
 hipError_t launch_gram(pwa_prec prec, const void *A, const void *w, int64_t n, int64_t ld, int k,

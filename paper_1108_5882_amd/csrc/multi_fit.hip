@@ -1,0 +1,213 @@
+// Many independent fits in one persistent launch (Berger, Section 2: fits are
+// repeated from many starting points and models, each needing the likelihood
+// of Eq. 2 and its gradient at every iteration).
+//
+// Every fit f has its own samples (N_D, N_MC, K_f) and its own trial vector.
+// The rows of all fits are cut into work items (one sample of one fit, a
+// range of tiles); blocks take items from an atomic counter, stream the rows
+// of the item with the fused single-V arithmetic (FP32 storage, FP64 z, I,
+// z/I and sums) and write one FP64 partial per item.  Because each item has
+// its own slot, results do not depend on which block took which item.  A
+// combine kernel adds each fit's item partials in item order and forms NLL
+// and gradient; a minimiser kernel then advances each fit's L-BFGS state.
+// The three kernels are captured once in a HIP graph and replayed per step.
+//
+// Row widths differ between fits (K from 4 to 48): each item carries its
+// width and the block dispatches to the compiled tile shape for it.
+#include "nll_stream_impl.hpp"
+
+namespace pwa {
+namespace {
+
+using stream_detail::EventMath;
+using stream_detail::Stage;
+
+constexpr int kMT = kStreamThreads;     // threads per block
+constexpr int kMW = kMT / 64;
+
+// Streams tiles [t0, t1) of one sample with shape (L, C, U); waves take tiles
+// t0 + wave, t0 + wave + kMW, ...; returns the block's partial in red.
+constexpr int kRedSlot = 2 * 3 + 1;      // largest 2C + 1 of the shapes below
+
+template <int L, int C, int U, int SEG>
+__device__ void multi_item(const MultiItem &it, const MultiFit &fit, double *slot, double *red) {
+    constexpr int SLOT = 2 * C + 1;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int g = lane / L, j = lane % L;
+    const float *A = SEG ? fit.A_mc : fit.A_data;
+    const float *W = SEG ? fit.w_mc : nullptr;
+    const int64_t n = SEG ? fit.n_mc : fit.n_data;
+    const double *V = fit.V;
+    double vr[C], vi[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int a = j * C + c;
+        vr[c] = a < fit.k ? V[2 * a] : 0.0;
+        vi[c] = a < fit.k ? V[2 * a + 1] : 0.0;
+    }
+    double acc_t = 0.0, acc_r[C], acc_i[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc_r[c] = acc_i[c] = 0.0;
+    int64_t t = it.t0 + wid;
+    if (t < it.t1) {
+        Stage<float, L, C, U, SEG> s0, s1;
+        s0.load(A, W, n, fit.ld, t, g, j);
+        for (;;) {
+            s1.load(A, W, n, fit.ld, t + kMW, g, j);
+            s0.compute(n, t, g, vr, vi, acc_t, acc_r, acc_i);
+            t += kMW;
+            if (t >= it.t1) break;
+            s0.load(A, W, n, fit.ld, t + kMW, g, j);
+            s1.compute(n, t, g, vr, vi, acc_t, acc_r, acc_i);
+            t += kMW;
+            if (t >= it.t1) break;
+        }
+    }
+#pragma unroll
+    for (int off = L; off < 64; off <<= 1) {
+        acc_t += __shfl_xor(acc_t, off);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            acc_r[c] += __shfl_xor(acc_r[c], off);
+            acc_i[c] += __shfl_xor(acc_i[c], off);
+        }
+    }
+    auto R = [&](int w, int jj, int s_) -> double & { return red[(w * 64 + jj) * SLOT + s_]; };
+    if (lane < L) {
+        R(wid, j, 0) = acc_t;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            R(wid, j, 1 + 2 * c) = acc_r[c];
+            R(wid, j, 2 + 2 * c) = acc_i[c];
+        }
+    }
+    __syncthreads();
+    const int ps = 1 + 2 * L * C;
+    for (int idx = threadIdx.x; idx < ps; idx += kMT) {
+        double s = 0.0;
+        if (idx == 0) {
+            for (int w = 0; w < kMW; ++w) s += R(w, 0, 0);
+        } else {
+            const int a = (idx - 1) >> 1, q = (idx - 1) & 1;
+            for (int w = 0; w < kMW; ++w) s += R(w, a / C, 1 + 2 * (a % C) + q);
+        }
+        slot[idx] = s;
+    }
+    __syncthreads();
+}
+
+template <int SEG>
+__device__ void dispatch_item(const MultiItem &it, const MultiFit &fit, double *slot, double *red) {
+    switch (fit.ld) {
+        case 4: multi_item<2, 2, 4, SEG>(it, fit, slot, red); break;
+        case 6: multi_item<2, 3, 2, SEG>(it, fit, slot, red); break;
+        case 8: multi_item<4, 2, 4, SEG>(it, fit, slot, red); break;
+        case 12: multi_item<4, 3, 2, SEG>(it, fit, slot, red); break;
+        case 16: multi_item<8, 2, 4, SEG>(it, fit, slot, red); break;
+        case 24: multi_item<8, 3, 2, SEG>(it, fit, slot, red); break;
+        case 32: multi_item<16, 2, 4, SEG>(it, fit, slot, red); break;
+        case 48: multi_item<16, 3, 2, SEG>(it, fit, slot, red); break;
+        default: break;
+    }
+}
+
+__global__ __launch_bounds__(kMT) void multi_stream_kernel(MultiArgs p) {
+    __shared__ int s_item;
+    __shared__ double red[kMW * 64 * kRedSlot];
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(p.item_counter, 1u);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= p.n_items) break;
+        const MultiItem it = p.items[item];
+        const MultiFit fit = p.fits[it.fit];
+        double *slot = p.partials + (int64_t)item * kMultiSlot;
+        if (it.seg == 0)
+            dispatch_item<0>(it, fit, slot, red);
+        else
+            dispatch_item<1>(it, fit, slot, red);
+    }
+}
+
+// One block per fit: adds the fit's item partials in item order and forms
+// NLL and gradient (Eq. 2 form), written to out[fit][2k + 2].
+__global__ __launch_bounds__(128) void multi_combine_kernel(MultiArgs p) {
+    __shared__ double tot[2][1 + 2 * PWA_MAX_K];
+    __shared__ double s_c;
+    const int f = blockIdx.x, tid = threadIdx.x;
+    const MultiFit fit = p.fits[f];
+    const int k = fit.k, ps = 1 + 2 * (int)fit.ld;
+    for (int idx = tid; idx < 2 * ps; idx += 128) {
+        const int sg = idx / ps, cc = idx % ps;
+        const int i0 = sg ? fit.item_mc0 : fit.item_data0;
+        const int i1 = sg ? fit.item_mc1 : fit.item_data1;
+        double s = 0.0;
+        for (int i = i0; i < i1; ++i) s += p.partials[(int64_t)i * kMultiSlot + cc];
+        tot[sg][cc] = s;
+    }
+    __syncthreads();
+    double *out = p.out + (int64_t)f * kMultiOut;
+    if (tid == 0) {
+        const double nd = (double)fit.n_data;
+        const double sum_log = tot[0][0] * EventMath<float>::kLogScale;
+        const double s_raw = tot[1][0];
+        double nll, c;
+        unsigned flags = 0;
+        if (nd == 0.0) {
+            nll = 0.0;
+            c = 0.0;
+        } else {
+            const double S = s_raw / fit.n_gen;
+            nll = -sum_log + nd * log(S);
+            c = nd / s_raw;
+            if (!isfinite(nll) || !(S > 0.0)) {
+                nll = INFINITY;
+                flags = 1;
+            }
+        }
+        out[0] = nll;
+        out[1 + 2 * k] = (double)flags;
+        s_c = c;
+    }
+    __syncthreads();
+    for (int i = tid; i < 2 * k; i += 128) out[1 + i] = 2.0 * (-tot[0][1 + i] + s_c * tot[1][1 + i]);
+    if (f == 0 && tid == 0) *p.item_counter = 0u;      // ready for the next launch
+}
+
+}  // namespace
+
+hipError_t launch_multi_eval(const MultiArgs &args, int blocks, hipStream_t stream) {
+    hipLaunchKernelGGL(multi_stream_kernel, dim3(blocks), dim3(kMT), 0, stream, args);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(multi_combine_kernel, dim3(args.n_fits), dim3(128), 0, stream, args);
+    return hipGetLastError();
+}
+
+bool multi_ld_supported(int64_t ld) {
+    return ld == 4 || ld == 6 || ld == 8 || ld == 12 || ld == 16 || ld == 24 || ld == 32 || ld == 48;
+}
+
+int64_t multi_layout_ld(int k) {
+    static const int widths[] = {4, 6, 8, 12, 16, 24, 32, 48};
+    for (int w : widths)
+        if (w >= k) return w;
+    return -1;
+}
+
+int multi_rows_per_tile(int64_t ld) {
+    switch (ld) {
+        case 4: return 32 * 4;
+        case 6: return 32 * 2;
+        case 8: return 16 * 4;
+        case 12: return 16 * 2;
+        case 16: return 8 * 4;
+        case 24: return 8 * 2;
+        case 32: return 4 * 4;
+        case 48: return 4 * 2;
+        default: return 0;
+    }
+}
+
+}  // namespace pwa

@@ -1,0 +1,129 @@
+"""GPU parity of the multi-fit path: one persistent launch evaluates many uneven fits
+(against the FP64 oracle, 1e-6), and the graph-captured L-BFGS iteration follows the
+reference L-BFGS of oracle/lbfgs.py."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle.lbfgs import LbfgsOracle
+from tests.tolerance import errors, reference
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _fits(spec, seed=0, weighted=False):
+    samples, V0 = [], []
+    for f, (nd, nm, k) in enumerate(spec):
+        s = synth.make_sample(3, n_data=nd, n_mc=nm, k=k, seed=seed, fit=f, weighted=weighted,
+                              dtype=np.complex64)
+        samples.append((s.A_data, s.A_mc, s.w_mc, s.n_gen))
+        V0.append(synth.eval_vectors(3, 1, k, seed=seed, stream=f)[0])
+    return samples, V0
+
+
+SPEC = [(3001, 9001, 4), (2000, 11000, 5), (1500, 7000, 7), (4097, 8192, 9), (2500, 9000, 13),
+        (6000, 20011, 16), (1000, 5000, 20), (3000, 8000, 24), (2000, 6000, 31), (2500, 7000, 32),
+        (1200, 4000, 40), (1800, 5000, 48), (0, 300, 6)]
+
+
+def test_multi_eval_parity():
+    from paper_1108_5882_amd import MultiFit
+    _say("case multi eval")
+    samples, V0 = _fits(SPEC, weighted=True)
+    mf = MultiFit(samples, V0)
+    nll, grads = mf.eval(V0)
+    for f, ((Ad, Am, w, ng), v) in enumerate(zip(samples, V0)):
+        if Ad.shape[0] == 0:
+            assert nll[f] == 0.0 and np.all(grads[f] == 0)
+            continue
+        e_n, e_g = errors(reference(Ad, Am, v, w=w, n_gen=ng), nll[f], grads[f])
+        _say(f"  fit {f} k={Ad.shape[1]} e_nll={e_n:.2e} e_grad={e_g:.2e}")
+        assert e_n < 1e-6 and e_g < 1e-6, f
+    # work-item sizes and grid sizes change nothing but the summation order
+    cfg, ms = mf.autotune(reps=2)
+    _say(f"  autotune {cfg} {ms:.3f} ms")
+    nll2, grads2 = mf.eval(V0)
+    for f in range(len(SPEC)):
+        if SPEC[f][0]:
+            assert abs(nll2[f] - nll[f]) <= 1e-9 * abs(nll[f])
+    mf.close()
+
+
+def test_multi_steps_follow_reference_lbfgs():
+    from paper_1108_5882_amd import MultiFit
+    spec = [(3000, 9000, 4), (4000, 12000, 8), (2500, 8000, 16), (2000, 7000, 24)]
+    samples, V0 = _fits(spec, seed=3)
+    mf = MultiFit(samples, V0)
+    T = 12
+    mf.step(T)
+    Vg, fg, stg, itg = mf.get()
+    for f, ((Ad, Am, w, ng), v0) in enumerate(zip(samples, V0)):
+        k = Ad.shape[1]
+
+        def fun(x, Ad=Ad, Am=Am):
+            return oracle.nll_grad(Ad, Am, x[0::2] + 1j * x[1::2])
+
+        x0 = np.empty(2 * k)
+        x0[0::2], x0[1::2] = v0.real, v0.imag
+        ref = LbfgsOracle(fun, x0)
+        for _ in range(T):
+            ref.step()
+        xg = np.empty(2 * k)
+        xg[0::2], xg[1::2] = Vg[f].real, Vg[f].imag
+        scale = np.sum(np.abs(np.log(oracle.intensity(Ad, ref.x[0::2] + 1j * ref.x[1::2])))) + Ad.shape[0]
+        _say(f"  fit {f}: f gpu {fg[f]:.10g} ref {ref.f:.10g} iters {itg[f]}/{ref.iter} "
+             f"dx {np.max(np.abs(xg - ref.x)) / np.max(np.abs(ref.x)):.2e}")
+        assert itg[f] == ref.iter
+        assert abs(fg[f] - ref.f) < 1e-6 * scale
+        assert np.max(np.abs(xg - ref.x)) < 1e-4 * np.max(np.abs(ref.x))
+    mf.close()
+
+
+def test_multi_graph_replays_are_deterministic():
+    from paper_1108_5882_amd import MultiFit
+    samples, V0 = _fits([(2000, 6000, 6), (3000, 9000, 12), (1000, 4000, 33)], seed=5)
+    mf = MultiFit(samples, V0)
+    mf.step(10)
+    a = mf.get()
+    # the same ten iterations as five pairs of replays with other GPU work in between
+    mf.reset(V0)
+    other = MultiFit(samples[:1], V0[:1])
+    for _ in range(5):
+        mf.step(2)
+        other.eval(V0[:1])
+    b = mf.get()
+    for f in range(3):
+        assert np.array_equal(a[0][f], b[0][f]) and a[1][f] == b[1][f]
+    other.close()
+    mf.close()
+
+
+def test_multi_uneven_family_reduced():
+    """The 64-fit family (N_D log-uniform, K uniform in 4..48, N_MC = 5 N_D) at 1% of its rows."""
+    from paper_1108_5882_amd import MultiFit
+    table = synth.multifit_table(64)
+    spec = [(max(100, nd // 100), max(500, nm // 100), k) for nd, k, nm in table]
+    samples, V0 = _fits(spec, seed=7)
+    mf = MultiFit(samples, V0)
+    mf.autotune(reps=2)
+    nll0, _ = mf.eval(V0)
+    mf.reset(V0)
+    ms = mf.step(20)
+    Vg, fg, st, it = mf.get()
+    _say(f"  64 fits: {ms:.3f} ms per iteration, accepted steps {it.min()}..{it.max()}")
+    assert np.all(fg <= nll0 + 1e-9 * np.abs(nll0))
+    assert np.all(it >= 1)
+    nll1, g1 = mf.eval(Vg)
+    for f in (0, 17, 40, 63):
+        Ad, Am, w, ng = samples[f]
+        e_n, e_g = errors(reference(Ad, Am, Vg[f]), nll1[f], g1[f])
+        assert e_n < 1e-6 and e_g < 1e-6, (f, e_n, e_g)
+    mf.close()
