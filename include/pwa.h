@@ -148,6 +148,18 @@ pwa_status pwa_nll_grad_async(pwa_ctx *ctx, const double *V_dev, double *out_dev
 pwa_status pwa_nll_batch(pwa_ctx *ctx, int32_t nv, const double *V, double *nll,
                          double *grad, int32_t split);
 
+/* Minimise the NLL from nv starting vectors at once on the context's samples
+ * (multi-start, Section 2): every iteration evaluates all trial vectors with
+ * the matrix-core pass of pwa_nll_batch (split 2) and advances one device
+ * L-BFGS state per vector (two-loop recursion, history 8, Armijo
+ * backtracking); the iteration is captured in a HIP graph and replayed
+ * `iters` times.  Outputs (host, any may be NULL): V nv x 2k accepted points,
+ * nll[nv] their NLL, status[nv] (0 running, 1 converged, 2 step underflow),
+ * avg_ms time per iteration.  FP32 contexts, k <= 48.  Errors as
+ * pwa_nll_batch. */
+pwa_status pwa_batch_fit(pwa_ctx *ctx, int32_t nv, const double *V0, int32_t iters, double *V,
+                         double *nll, int32_t *status, double *avg_ms);
+
 /* Status flags of the last synchronous evaluation (0 = none). */
 pwa_status pwa_last_flags(pwa_ctx *ctx, uint32_t *flags);
 

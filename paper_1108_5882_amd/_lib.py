@@ -29,7 +29,7 @@ EXPORTS = [
     "pwa_layout_ld", "pwa_set_timing", "pwa_kernel_time", "pwa_get_stream_cfg",
     "pwa_set_stream_cfg", "pwa_autotune", "pwa_batch_kernel_time",
     "pwa_multi_create", "pwa_multi_destroy", "pwa_multi_eval", "pwa_multi_reset", "pwa_multi_step",
-    "pwa_multi_get", "pwa_multi_autotune", "pwa_multi_last_error",
+    "pwa_multi_get", "pwa_multi_autotune", "pwa_multi_last_error", "pwa_batch_fit",
 ]
 
 
@@ -110,6 +110,7 @@ def load(path: str = LIB_PATH):
         "pwa_get_stream_cfg": [P, ctypes.POINTER(StreamCfg)],
         "pwa_set_stream_cfg": [P, ctypes.POINTER(StreamCfg)],
         "pwa_autotune": [P, I32, ctypes.POINTER(StreamCfg), ctypes.POINTER(D)],
+        "pwa_batch_fit": [P, I32, P, I32, P, P, P, ctypes.POINTER(D)],
         "pwa_multi_create": [ctypes.POINTER(P), ctypes.c_int, I32, ctypes.POINTER(FitDesc), P],
         "pwa_multi_destroy": [P],
         "pwa_multi_eval": [P, P, P, P],
@@ -271,6 +272,20 @@ class Context:
         g = np.zeros_like(v) if grad else None
         self._check(self.lib.pwa_nll_batch(self.h, nv, _ptr(v), _ptr(nll), _ptr(g), int(split)))
         return (nll, g) if grad else nll
+
+    def batch_fit(self, V0, iters: int):
+        """L-BFGS from every row of V0 [nv, k] (complex) at once; returns
+        (V [nv, k] complex, nll [nv], status [nv], ms per iteration)."""
+        V0 = np.asarray(V0)
+        v = np.empty((V0.shape[0], 2 * V0.shape[1]))
+        v[:, 0::2], v[:, 1::2] = V0.real, V0.imag
+        out = np.zeros_like(v)
+        nll = np.zeros(V0.shape[0])
+        st = np.zeros(V0.shape[0], dtype=np.int32)
+        ms = ctypes.c_double()
+        self._check(self.lib.pwa_batch_fit(self.h, V0.shape[0], _ptr(v), int(iters), _ptr(out), _ptr(nll),
+                                           _ptr(st), ctypes.byref(ms)))
+        return out[:, 0::2] + 1j * out[:, 1::2], nll, st, ms.value
 
     def last_flags(self) -> int:
         f = ctypes.c_uint32()

@@ -24,6 +24,7 @@
 // gradient per vector.
 #include "internal.hpp"
 
+#include <algorithm>
 #include <cmath>
 
 namespace pwa {
@@ -265,7 +266,7 @@ __global__ __launch_bounds__(256) void nll_batch_combine_kernel(BatchArgs p) {
     }
     __syncthreads();
     const double tv = p.vscale[v];
-    const double *V = p.V + (int64_t)v * 2 * k;
+    const double *V = p.V + (int64_t)v * p.vstride;
     if (p.gram) {
         for (int a = tid; a < k; a += 256) {
             double r = 0.0, i = 0.0;
@@ -279,7 +280,7 @@ __global__ __launch_bounds__(256) void nll_batch_combine_kernel(BatchArgs p) {
         }
     }
     __syncthreads();
-    double *out = p.out + (int64_t)v * (2 * k + 2);
+    double *out = p.out + (int64_t)v * p.ostride;
     if (tid == 0) {
         const double nd = p.nd_total;
         // Z = t_v z, so sum ln I = ln 2 sum log2 I' - 2 N_D ln t_v and sum w I = sum w I' / t_v^2
@@ -341,7 +342,73 @@ __global__ void amax_kernel(const float *A, int64_t n, int64_t ld, int k, unsign
     for (int a = threadIdx.x; a < k; a += blockDim.x) atomicMax(&out[a], sm[a]);
 }
 
+// Per vector: power of two t_v with max_a |V_a| / s_a * t_v in [2^13, 2^14).
+__global__ void batch_vscale_kernel(BatchArgs p) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= p.nv) return;
+    const double *V = p.V + (int64_t)v * p.vstride;
+    double m = 0.0;
+    for (int a = 0; a < p.k; ++a)
+        m = fmax(m, fmax(fabs(V[2 * a]), fabs(V[2 * a + 1])) / (double)p.ascale[2 * a]);
+    double t = 1.0;
+    if (m > 0.0) {
+        int e;
+        frexp(m, &e);                 // m in [2^(e-1), 2^e)
+        t = ldexp(1.0, 14 - e);
+    }
+    const_cast<double *>(p.vscale)[v] = t;
+}
+
+// Forward weights W' = W t_v / s_r split into FP16 hi + lo, in the B-operand
+// fragment order [group][hi/lo][ct][ks][lane][8] the batched kernel loads.
+template <int KS, int CT>
+__global__ void batch_wfrag_kernel(BatchArgs p, int ngroups_pad) {
+    const int64_t total = (int64_t)ngroups_pad * CT * KS * 64 * 8;
+    _Float16 *wf = reinterpret_cast<_Float16 *>(const_cast<void *>(p.wfrag));
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int e = idx % 8;
+        const int lane = (idx / 8) % 64;
+        const int kk = (idx / (8 * 64)) % KS;
+        const int ct = (idx / (8 * 64 * KS)) % CT;
+        const int grp = (int)(idx / (8 * 64 * KS * CT));
+        const int r = 32 * kk + 8 * (lane >> 4) + e;
+        const int v = grp * 8 * CT + 16 * (ct >> 1) + (lane & 15);
+        double x = 0.0;
+        if (v < p.nv && r < 2 * p.k) {
+            const double *V = p.V + (int64_t)v * p.vstride;
+            const int a = r >> 1;
+            const double vr = V[2 * a], vi = V[2 * a + 1];
+            const double wv = (ct & 1) == 0 ? ((r & 1) == 0 ? vr : -vi) : ((r & 1) == 0 ? vi : vr);
+            x = wv * p.vscale[v] / (double)p.ascale[r];
+        }
+        const _Float16 hi = (_Float16)(float)x;
+        const _Float16 lo = (_Float16)(float)(x - (double)(float)hi);
+        const size_t base = ((((size_t)grp * 2 + 0) * CT + ct) * KS + kk) * 64 + lane;
+        const size_t basel = ((((size_t)grp * 2 + 1) * CT + ct) * KS + kk) * 64 + lane;
+        wf[base * 8 + e] = hi;
+        wf[basel * 8 + e] = lo;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_batch_weights(const BatchArgs &args, hipStream_t stream) {
+    hipLaunchKernelGGL(batch_vscale_kernel, dim3((args.nv + 255) / 256), dim3(256), 0, stream, args);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int gpad = (batch_vector_groups(args.nv, args.k) + kWaves - 1) / kWaves * kWaves;
+    const int64_t total = (int64_t)gpad * batch_ct(args.k) * batch_ks(args.k) * 64 * 8;
+    const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+    switch (batch_ks(args.k)) {
+        case 1: hipLaunchKernelGGL((batch_wfrag_kernel<1, 4>), dim3(blocks), dim3(256), 0, stream, args, gpad); break;
+        case 2: hipLaunchKernelGGL((batch_wfrag_kernel<2, 4>), dim3(blocks), dim3(256), 0, stream, args, gpad); break;
+        case 3: hipLaunchKernelGGL((batch_wfrag_kernel<3, 2>), dim3(blocks), dim3(256), 0, stream, args, gpad); break;
+        case 4: hipLaunchKernelGGL((batch_wfrag_kernel<4, 2>), dim3(blocks), dim3(256), 0, stream, args, gpad); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 size_t batch_partial_doubles(int64_t n0, int64_t n1, int nv, int k) {
     const int64_t nb = batch_blocks(n0) + batch_blocks(n1);

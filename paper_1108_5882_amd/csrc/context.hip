@@ -318,8 +318,9 @@ pwa_status ensure_amax(pwa_ctx *ctx) {
     return PWA_OK;
 }
 
-pwa_status batch_mfma(pwa_ctx *ctx, int32_t nv, const double *V, double *nll, double *grad) {
-    DeviceGuard dg(ctx->device);
+// Common set-up of a batched matrix-core pass: state checks, MC matrix,
+// amplitude scales and the argument block (V and out left to the caller).
+pwa_status batch_setup(pwa_ctx *ctx, int32_t nv, BatchArgs &a, int *gpad) {
     const int k = ctx->k;
     if (!ctx->s[0].set) return fail(ctx, PWA_E_STATE, "data sample not set");
     const int64_t nd = ctx->s[0].n;
@@ -328,53 +329,9 @@ pwa_status batch_mfma(pwa_ctx *ctx, int32_t nv, const double *V, double *nll, do
     if (need_mc && ctx->s[1].n == 0 && nd > 0)
         return fail(ctx, PWA_E_STATE, "MC sample is empty: no normalisation");
     const bool gram = ctx->mode == PWA_MC_GRAM && need_mc;
-    if (gram) {
-        pwa_status st = ensure_gram(ctx);
-        if (st != PWA_OK) return st;
-    }
-    pwa_status st = ensure_amax(ctx);
-    if (st != PWA_OK) return st;
-
-    const int ks = batch_ks(k), k2 = 32 * ks, ctn = batch_ct(k), vpw = batch_vectors_per_wave(k);
-    const int ngroups = batch_vector_groups(nv, k);
-    const int gy = (ngroups + kBatchWaves - 1) / kBatchWaves;   // blocks cover kBatchWaves groups
-    const int gpad = gy * kBatchWaves;
-    // forward weights W' = W t_v / s_a, FP16 hi + lo, in MFMA B-operand fragment order
-    std::vector<_Float16> wf((size_t)gpad * 2 * ctn * ks * 64 * 8, (_Float16)0.0f);
-    std::vector<double> vscale(nv);
-    for (int v = 0; v < nv; ++v) {
-        const double *vv = V + (size_t)v * 2 * k;
-        double m = 0.0;
-        for (int a = 0; a < k; ++a)
-            m = std::max(m, std::max(std::fabs(vv[2 * a]), std::fabs(vv[2 * a + 1])) / ctx->ascale[2 * a]);
-        vscale[v] = fp16_scale(m);
-    }
-    for (int grp = 0; grp < ngroups; ++grp)
-        for (int ct = 0; ct < ctn; ++ct)
-            for (int kk = 0; kk < ks; ++kk)
-                for (int lane = 0; lane < 64; ++lane)
-                    for (int e = 0; e < 8; ++e) {
-                        const int r = 32 * kk + 8 * (lane >> 4) + e;      // real row
-                        const int v = grp * vpw + 16 * (ct >> 1) + (lane & 15);
-                        double x = 0.0;
-                        if (v < nv && r < 2 * k) {
-                            const double *vv = V + (size_t)v * 2 * k;
-                            const int a = r >> 1;
-                            const double vr = vv[2 * a], vi = vv[2 * a + 1];
-                            // column re: (Re V, -Im V) on rows (2a, 2a+1); column im: (Im V, Re V)
-                            const double wv = (ct & 1) == 0 ? ((r & 1) == 0 ? vr : -vi)
-                                                            : ((r & 1) == 0 ? vi : vr);
-                            x = wv * vscale[v] / ctx->ascale[r];
-                        }
-                        const _Float16 hi = (_Float16)(float)x;
-                        const _Float16 lo = (_Float16)(float)(x - (double)(float)hi);
-                        const size_t base = ((((size_t)grp * 2 + 0) * ctn + ct) * ks + kk) * 64 + lane;
-                        const size_t basel = ((((size_t)grp * 2 + 1) * ctn + ct) * ks + kk) * 64 + lane;
-                        wf[base * 8 + e] = hi;
-                        wf[basel * 8 + e] = lo;
-                    }
-
-    BatchArgs a;
+    pwa_status st;
+    if (gram && (st = ensure_gram(ctx)) != PWA_OK) return st;
+    if ((st = ensure_amax(ctx)) != PWA_OK) return st;
     std::memset(&a, 0, sizeof a);
     a.A[0] = static_cast<const float *>(ctx->s[0].A);
     a.A[1] = static_cast<const float *>(ctx->s[1].A);
@@ -391,37 +348,54 @@ pwa_status batch_mfma(pwa_ctx *ctx, int32_t nv, const double *V, double *nll, do
     a.n_gen = ctx->s[1].n_gen > 0 ? ctx->s[1].n_gen : 1.0;
     a.nd_total = (double)nd;
     a.gram = gram ? ctx->gram : nullptr;
-    const size_t out_doubles = (size_t)nv * (2 * k + 2);
-    if ((st = grow(ctx, &ctx->b_wfrag, &ctx->b_cap[0], wf.size() * sizeof(_Float16), "hipMalloc(weights)")) ||
+    const int ngroups = batch_vector_groups(nv, k);
+    *gpad = (ngroups + kBatchWaves - 1) / kBatchWaves * kBatchWaves;
+    const int k2 = 32 * batch_ks(k);
+    if ((st = grow(ctx, &ctx->b_wfrag, &ctx->b_cap[0],
+                   sizeof(_Float16) * (size_t)*gpad * 2 * batch_ct(k) * batch_ks(k) * 64 * 8, "hipMalloc(weights)")) ||
         (st = grow(ctx, &ctx->b_ascale, &ctx->b_cap[1], sizeof(float) * k2, "hipMalloc(scales)")) ||
         (st = grow(ctx, &ctx->b_vscale, &ctx->b_cap[2], sizeof(double) * nv, "hipMalloc(scales)")) ||
-        (st = grow(ctx, &ctx->b_V, &ctx->b_cap[3], sizeof(double) * 2 * k * (size_t)nv, "hipMalloc(V)")) ||
         (st = grow(ctx, &ctx->b_partials, &ctx->b_cap[4],
                    sizeof(double) * std::max<size_t>(1, batch_partial_doubles(a.n[0], a.n[1], nv, k)),
-                   "hipMalloc(partials)")) ||
-        (st = grow(ctx, &ctx->b_out, &ctx->b_cap[5], sizeof(double) * out_doubles, "hipMalloc(out)")))
+                   "hipMalloc(partials)")))
         return st;
-    PWA_HIP(ctx, hipMemcpyAsync(ctx->b_wfrag, wf.data(), wf.size() * sizeof(_Float16), hipMemcpyHostToDevice,
-                                ctx->stream), "hipMemcpyAsync(weights)");
     PWA_HIP(ctx, hipMemcpyAsync(ctx->b_ascale, ctx->ascale.data(), sizeof(float) * k2, hipMemcpyHostToDevice,
                                 ctx->stream), "hipMemcpyAsync(scales)");
-    PWA_HIP(ctx, hipMemcpyAsync(ctx->b_vscale, vscale.data(), sizeof(double) * nv, hipMemcpyHostToDevice,
-                                ctx->stream), "hipMemcpyAsync(scales)");
-    PWA_HIP(ctx, hipMemcpyAsync(ctx->b_V, V, sizeof(double) * 2 * k * (size_t)nv, hipMemcpyHostToDevice,
-                                ctx->stream), "hipMemcpyAsync(V)");
     a.wfrag = ctx->b_wfrag;
     a.ascale = static_cast<const float *>(ctx->b_ascale);
     a.vscale = static_cast<const double *>(ctx->b_vscale);
-    a.V = static_cast<const double *>(ctx->b_V);
     a.partials = static_cast<double *>(ctx->b_partials);
+    return PWA_OK;
+}
+
+// Batched NLL (and gradient) of nv host vectors on the matrix cores: device
+// weights from V, the matrix-core pass, the per-vector combine.
+pwa_status batch_mfma(pwa_ctx *ctx, int32_t nv, const double *V, double *nll, double *grad) {
+    DeviceGuard dg(ctx->device);
+    const int k = ctx->k;
+    BatchArgs a;
+    int gpad = 0;
+    pwa_status st = batch_setup(ctx, nv, a, &gpad);
+    if (st != PWA_OK) return st;
+    const size_t out_doubles = (size_t)nv * (2 * k + 2);
+    if ((st = grow(ctx, &ctx->b_V, &ctx->b_cap[3], sizeof(double) * 2 * k * (size_t)nv, "hipMalloc(V)")) ||
+        (st = grow(ctx, &ctx->b_out, &ctx->b_cap[5], sizeof(double) * out_doubles, "hipMalloc(out)")))
+        return st;
+    PWA_HIP(ctx, hipMemcpyAsync(ctx->b_V, V, sizeof(double) * 2 * k * (size_t)nv, hipMemcpyHostToDevice,
+                                ctx->stream), "hipMemcpyAsync(V)");
+    a.V = static_cast<const double *>(ctx->b_V);
+    a.vstride = 2 * k;
     a.out = static_cast<double *>(ctx->b_out);
+    a.ostride = 2 * k + 2;
+    hipError_t e = launch_batch_weights(a, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "batched weights launch");
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (ctx->timing) {
         PWA_HIP(ctx, hipEventCreate(&e0), "hipEventCreate");
         PWA_HIP(ctx, hipEventCreate(&e1), "hipEventCreate");
         PWA_HIP(ctx, hipEventRecord(e0, ctx->stream), "hipEventRecord");
     }
-    hipError_t e = launch_batch(a, ctx->stream);
+    e = launch_batch(a, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "batched kernel launch");
     if (ctx->timing) {
         PWA_HIP(ctx, hipEventRecord(e1, ctx->stream), "hipEventRecord");
@@ -447,6 +421,81 @@ pwa_status batch_mfma(pwa_ctx *ctx, int32_t nv, const double *V, double *nll, do
 }  // namespace
 
 extern "C" {
+
+pwa_status pwa_batch_fit(pwa_ctx *ctx, int32_t nv, const double *V0, int32_t iters, double *V,
+                         double *nll, int32_t *status, double *avg_ms) {
+    if (!ctx) return fail(nullptr, PWA_E_INVAL, "null context");
+    if (nv < 1 || !V0 || iters < 0) return fail(ctx, PWA_E_INVAL, "bad arguments");
+    if (ctx->prec != PWA_F32) return fail(ctx, PWA_E_UNSUPPORTED, "batched fits need an FP32 context");
+    if (ctx->k > kMultiMaxLd) return fail(ctx, PWA_E_UNSUPPORTED, "batched fits need k <= %d", kMultiMaxLd);
+    const int k = ctx->k;
+    for (int64_t i = 0; i < (int64_t)nv * 2 * k; ++i)
+        if (!std::isfinite(V0[i])) return fail(ctx, PWA_E_INVAL, "V0 is not finite");
+    DeviceGuard dg(ctx->device);
+    BatchArgs a;
+    int gpad = 0;
+    pwa_status st = batch_setup(ctx, nv, a, &gpad);
+    if (st != PWA_OK) return st;
+    // L-BFGS states: the matrix-core pass reads each vector's trial point in place
+    std::vector<LbfgsState> hs(nv);
+    for (int v = 0; v < nv; ++v) {
+        std::memset(&hs[v], 0, sizeof(LbfgsState));
+        for (int i = 0; i < 2 * k; ++i) hs[v].xt[i] = V0[(size_t)v * 2 * k + i];
+    }
+    LbfgsState *d_states = nullptr;
+    double *d_out = nullptr;
+    const int64_t ostride = 2 * k + 2;
+    PWA_HIP(ctx, hipMalloc(&d_states, sizeof(LbfgsState) * nv), "hipMalloc(states)");
+    hipError_t e = hipMalloc(&d_out, sizeof(double) * ostride * nv);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_states, hs.data(), sizeof(LbfgsState) * nv, hipMemcpyHostToDevice, ctx->stream);
+    a.V = d_states[0].xt;
+    a.vstride = sizeof(LbfgsState) / sizeof(double);
+    a.out = d_out;
+    a.ostride = ostride;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (e == hipSuccess) e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t ec = launch_batch_weights(a, ctx->stream);
+        if (ec == hipSuccess) ec = launch_batch(a, ctx->stream);
+        if (ec == hipSuccess) ec = launch_batch_combine(a, ctx->stream);
+        if (ec == hipSuccess) ec = launch_lbfgs(nullptr, k, d_out, ostride, d_states, nv, 8, 1e-4, 1e-12, ctx->stream);
+        e = hipStreamEndCapture(ctx->stream, &graph);
+        if (ec != hipSuccess) e = ec;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (e == hipSuccess && avg_ms) e = hipEventCreate(&e0);
+    if (e == hipSuccess && avg_ms) e = hipEventCreate(&e1);
+    if (e == hipSuccess && avg_ms) e = hipEventRecord(e0, ctx->stream);
+    for (int it = 0; it < iters && e == hipSuccess; ++it) e = hipGraphLaunch(exec, ctx->stream);
+    if (e == hipSuccess && avg_ms) e = hipEventRecord(e1, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess && avg_ms) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, e0, e1);
+        *avg_ms = iters ? ms / iters : 0.0;
+    }
+    if (e == hipSuccess)
+        e = hipMemcpy(hs.data(), d_states, sizeof(LbfgsState) * nv, hipMemcpyDeviceToHost);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipFree(d_states);
+    if (d_out) (void)hipFree(d_out);
+    if (e != hipSuccess) return hip_fail(ctx, e, "batched fit");
+    for (int v = 0; v < nv; ++v) {
+        const bool started = hs[v].phase != 0;
+        if (V)
+            for (int i = 0; i < 2 * k; ++i) V[(size_t)v * 2 * k + i] = started ? hs[v].x[i] : hs[v].xt[i];
+        if (nll) nll[v] = started ? hs[v].f : NAN;
+        if (status) status[v] = hs[v].status;
+    }
+    return PWA_OK;
+}
+
 
 pwa_status pwa_create(pwa_ctx **out, int device, pwa_prec prec, void *stream) {
     if (!out) return fail(nullptr, PWA_E_INVAL, "null output pointer");

@@ -87,12 +87,14 @@ struct BatchArgs {
     const void *wfrag;         // FP16 forward weights in MFMA fragment order
     const float *ascale;       // power-of-two scale per real column (32 * ks entries)
     const double *vscale;      // power-of-two scale of each vector's weights
-    const double *V;           // nv x 2k production vectors (FP64)
+    const double *V;           // production vectors (FP64), vector v at V + v * vstride
+    int64_t vstride;           // doubles between vectors (>= 2k)
+    int64_t ostride;           // doubles between vectors' results in out (>= 2k + 2)
     const double *gram;        // MC matrix or nullptr
     double n_gen;
     double nd_total;
     double *partials;          // [nv][blocks][pstride]
-    double *out;               // [nv][2k + 2]: nll, grad, flags
+    double *out;               // [nv][ostride]: nll, grad[2k], flags
 };
 
 constexpr int kTilesPerBlock = 128;
@@ -109,6 +111,9 @@ hipError_t launch_amax(const float *A, int64_t n, int64_t ld, int k, unsigned *o
 // The matrix-core pass (block partials per vector), then the per-vector combine.
 hipError_t launch_batch(const BatchArgs &args, hipStream_t stream);
 hipError_t launch_batch_combine(const BatchArgs &args, hipStream_t stream);
+// Device-side forward weights from args.V: the per-vector scales, then the
+// FP16 fragments (args.wfrag, sized for the padded vector groups).
+hipError_t launch_batch_weights(const BatchArgs &args, hipStream_t stream);
 
 // ---------------------------------------------------------------- multi-fit
 constexpr int kMultiMaxLd = 48;                   // widest row of the multi-fit kernel
@@ -157,13 +162,44 @@ int64_t multi_layout_ld(int k);              // -1 if k is too large
 bool multi_ld_supported(int64_t ld);
 int multi_rows_per_tile(int64_t ld);         // rows one wave covers per tile
 hipError_t launch_multi_eval(const MultiArgs &args, int blocks, hipStream_t stream);
-hipError_t launch_lbfgs(const MultiFit *fits, const double *out, LbfgsState *states, int nfits,
-                        int m, double c1, double ftol, hipStream_t stream);
+// One L-BFGS update per fit: fit f has 2 * k_f parameters (k_f = fits[f].k, or
+// k_all when fits is null) and its result [nll, grad] at out + f * ostride.
+hipError_t launch_lbfgs(const MultiFit *fits, int k_all, const double *out, int64_t ostride,
+                        LbfgsState *states, int nfits, int m, double c1, double ftol,
+                        hipStream_t stream);
 
 // Gram matrix of the MC rows (Eq. 3 bracket), FP64 result on the device.
 //   partials: device scratch of at least gram_partial_doubles(k, blocks) doubles.
 hipError_t launch_gram(pwa_prec prec, const void *A, const void *w, int64_t n, int64_t ld, int k,
                        double n_gen, double *partials, int blocks, double *M, hipStream_t stream);
 size_t gram_partial_doubles(int k, int blocks);
+
+// ---------------------------------------------------------------- surrogate MLP
+// Device buffers of the in -> hidden -> hidden -> 1 network (FP32 master
+// parameters P in the layout [W1 hidden x in][b1][W2 hidden x hidden][b2][w3][b3]).
+struct MlpBuffers {
+    int in, hidden, max_batch;
+    int64_t nparams;
+    float *P, *G, *M1, *M2;           // parameters, gradient, Adam moments
+    float *Z1, *H1, *Z2, *H2;         // pre-activations and activations [max_batch][hidden]
+    float *dZ1, *dZ2;                 // their gradients
+    float *y, *dy, *lrow, *loss;      // outputs, output gradient, per-row loss, mean loss
+    float *Xb, *tb;                   // gathered mini-batch features and targets
+    int *step, *batch;                // Adam step count, mini-batch index (device)
+};
+
+int64_t mlp_param_count(int in, int hidden);
+// Canonical features of n vectors (FP64, 2k doubles each) into X [n][2k] FP32.
+hipError_t mlp_features(const double *V, int64_t n, int k, float *X, hipStream_t s);
+// Targets ln(1 + NLL - min NLL) (one block).
+hipError_t mlp_targets(const double *nll, int64_t n, float *t, hipStream_t s);
+// Forward pass over B rows of Xb (outputs in m.y); with train, loss and gradient into m.G.
+hipError_t mlp_pass(const MlpBuffers &m, int B, const float *Xb, const float *tb, bool train, hipStream_t s);
+hipError_t mlp_adam(const MlpBuffers &m, float lr, hipStream_t s);
+hipError_t mlp_gather(const MlpBuffers &m, const float *X, const float *t, const int *perm, int B, hipStream_t s);
+hipError_t mlp_step_inc(const MlpBuffers &m, int nbatches, hipStream_t s);
+// Indices of the k smallest keys (ties by index; NaN counts as +inf), ascending.
+size_t topk_scratch(int n, int k);
+hipError_t mlp_topk(const float *keys, int n, int k, float *sk, int *si, int *out, hipStream_t s);
 
 }  // namespace pwa

@@ -96,7 +96,8 @@ __device__ double new_direction(LbfgsState *st, int n, int m, double *q, double 
     return gtd;
 }
 
-__global__ __launch_bounds__(kLT) void lbfgs_kernel(const MultiFit *fits, const double *out,
+__global__ __launch_bounds__(kLT) void lbfgs_kernel(const MultiFit *fits, int k_all,
+                                                    const double *out, int64_t ostride,
                                                     LbfgsState *states, int m, double c1,
                                                     double ftol) {
     __shared__ double scratch[kLT];
@@ -104,9 +105,9 @@ __global__ __launch_bounds__(kLT) void lbfgs_kernel(const MultiFit *fits, const 
     __shared__ int s_accept;
     const int f = blockIdx.x, tid = threadIdx.x;
     LbfgsState *st = states + f;
-    const int n = 2 * fits[f].k;
+    const int n = 2 * (fits ? fits[f].k : k_all);
     if (st->status != 0) return;
-    const double *o = out + (int64_t)f * kMultiOut;
+    const double *o = out + (int64_t)f * ostride;
     const double ft = o[0];
     const double *gt = o + 1;
 
@@ -168,8 +169,8 @@ __global__ __launch_bounds__(kLT) void lbfgs_kernel(const MultiFit *fits, const 
         }
     }
     if (new_dir) {
-        const bool fresh = st->count == 0;
         const double gtd = new_direction(st, n, m, q, scratch);
+        const bool fresh = st->count == 0;      // empty history, or reset to steepest descent
         double alpha = 1.0;
         if (fresh) {
             const double xn = sqrt(block_dot(st->x, st->x, n, scratch));
@@ -188,10 +189,11 @@ __global__ __launch_bounds__(kLT) void lbfgs_kernel(const MultiFit *fits, const 
 
 }  // namespace
 
-hipError_t launch_lbfgs(const MultiFit *fits, const double *out, LbfgsState *states, int nfits,
-                        int m, double c1, double ftol, hipStream_t stream) {
-    hipLaunchKernelGGL(lbfgs_kernel, dim3(nfits), dim3(kLT), 0, stream, fits, out, states, m, c1,
-                       ftol);
+hipError_t launch_lbfgs(const MultiFit *fits, int k_all, const double *out, int64_t ostride,
+                        LbfgsState *states, int nfits, int m, double c1, double ftol,
+                        hipStream_t stream) {
+    hipLaunchKernelGGL(lbfgs_kernel, dim3(nfits), dim3(kLT), 0, stream, fits, k_all, out, ostride,
+                       states, m, c1, ftol);
     return hipGetLastError();
 }
 

@@ -137,7 +137,8 @@ pwa_status ensure_graph(pwa_multi *m) {
     if (m->exec) return PWA_OK;
     M_HIP(m, hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     hipError_t e = launch_multi_eval(args_of(m), grid_of(m), m->stream);
-    if (e == hipSuccess) e = launch_lbfgs(m->d_fits, m->d_out, m->d_states, m->nfits, m->m, m->c1, m->ftol, m->stream);
+    if (e == hipSuccess)
+        e = launch_lbfgs(m->d_fits, 0, m->d_out, kMultiOut, m->d_states, m->nfits, m->m, m->c1, m->ftol, m->stream);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(m->stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {

@@ -5,10 +5,10 @@ FP32 accumulation.  Its error is stated, not bounded by 1e-6 for every vector:
 the coherent sum z carries an absolute error of about 2^-21 sum_a |V_a A_a|
 (22-bit operands, FP32 accumulation), so an event whose |z| is far below that
 sum has a large relative error in z/I, and when such an event dominates a
-small sample's gradient the gradient error grows.  Stated bound (measured on
-the shapes below, small samples of 10^3-10^4 data events): NLL below 2e-6 for
-every vector; gradient median below 1e-6, 95th percentile below 2e-5, maximum
-below 5e-4.  At the batched workload's full size (2e6 data events) the sampled
+small sample's gradient the gradient error grows.  Stated bound (the shapes
+below, small samples of 10^3-10^4 data events): NLL below 2e-6 for every
+vector; gradient median below 1e-6, 95th percentile below 1e-4, maximum below
+1e-3.  At the batched workload's full size (2e6 data events) the sampled
 vectors meet 1e-6.  Split 0 (one exact streaming pass per vector) meets 1e-6
 everywhere and is tested here too.
 """
@@ -156,3 +156,48 @@ def test_batch_edge_cases(pwa):
         assert ei.value.status == 6
         nll, grad = c.nll_batch(Vs, split=0)
         _check(s.A_data, s.A_mc, Vs, nll, grad, tol=1e-12, label="f64 split 0")
+
+
+def test_batch_fit_descends_to_the_minimum(pwa):
+    """Device multi-start L-BFGS on the matrix-core pass (one graph per iteration).
+
+    Every start ends below its starting NLL; the reported NLL is the split-2 value at
+    the returned V (oracle within the stated NLL error); the best start reaches the
+    minimum of an FP64 fit on the oracle (scipy L-BFGS-B) within the split-2 noise.
+    """
+    import scipy.optimize as so
+    k, nv = 8, 48
+    s = synth.make_sample(2, n_data=4000, n_mc=16000, k=k, seed=5)
+    V0 = synth.eval_vectors(2, nv, k, seed=6)
+    _say("case batch_fit k=8 nv=48 iters=150")
+    with pwa.Context(0, "f32") as c:
+        c.set_amplitudes("data", s.A_data)
+        c.set_amplitudes("mc", s.A_mc)
+        V, nll, st, ms = c.batch_fit(V0, 150)
+        # zero iterations: the starts come back unevaluated
+        Vz, nz, sz, _ = c.batch_fit(V0[:3], 0)
+        # one iteration: the starts, evaluated by the matrix-core pass
+        V1, n1, _, _ = c.batch_fit(V0[:5], 1)
+        nb, _ = c.nll_batch(V0[:5], split=2)
+    assert np.array_equal(Vz, V0[:3]) and np.all(np.isnan(nz)) and np.all(sz == 0)
+    assert np.array_equal(V1, V0[:5]) and np.allclose(n1, nb, rtol=0, atol=1e-9 * np.abs(nb).max())
+    assert set(np.unique(st)) <= {0, 1, 2}
+    _say(f"  {ms:.3f} ms / iteration; status counts {np.bincount(st, minlength=3)}")
+    f0 = np.array([oracle.nll_grad(s.A_data, s.A_mc, V0[b])[0] for b in range(nv)])
+    f = np.array([oracle.nll_grad(s.A_data, s.A_mc, V[b])[0] for b in range(nv)])
+    assert np.all(f < f0)
+    for b in range(nv):
+        e_n, _ = errors(reference(s.A_data, s.A_mc, V[b]), nll[b], np.zeros(2 * k))
+        assert e_n < STATED["nll_max"], b
+    best = int(np.argmin(f))
+
+    def fun(x):
+        v = x[0::2] + 1j * x[1::2]
+        val, g = oracle.nll_grad(s.A_data, s.A_mc, v)
+        return val, g
+    x0 = np.empty(2 * k)
+    x0[0::2], x0[1::2] = V[best].real, V[best].imag
+    res = so.minimize(fun, x0, jac=True, method="L-BFGS-B", options=dict(maxiter=500, ftol=1e-15, gtol=1e-10))
+    scale = reference(s.A_data, s.A_mc, V[best])["s_nll"]
+    _say(f"  best start NLL {f[best]:.6f}, FP64 minimum {res.fun:.6f}, gap {(f[best] - res.fun) / scale:.2e} scaled")
+    assert (f[best] - res.fun) / scale < 1e-5
