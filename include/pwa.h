@@ -272,6 +272,81 @@ pwa_status pwa_multi_autotune(pwa_multi *m, int32_t reps, int64_t *item_bytes, i
 
 const char *pwa_multi_last_error(const pwa_multi *m);
 
+/* ------------------------------------------------------------------------
+ * Surrogate of the NLL for screening starting points.  Fits are repeated
+ * from many starting points to find the global minimum (Section 2), and fits
+ * with many parameters are expensive (Section 4); a small network trained on
+ * exact (V, NLL) pairs ranks candidate starts cheaply, and only the best are
+ * refined with the exact likelihood (pwa_batch_fit).
+ *
+ * Network: in -> hidden -> hidden -> 1 with exact-erf GELU after both hidden
+ * layers, y = w3 . GELU(W2 GELU(W1 x + b1) + b2) + b3.  Parameters: one FP32
+ * array [W1 (hidden x in, row-major) | b1 | W2 (hidden x hidden) | b2 | w3 | b3]
+ * (FP32 master copy); matrix products round both operands to FP16 and
+ * accumulate in FP32 on the matrix cores; the head rounds its activations and
+ * weights to FP16 too.  Loss: mean squared error.  Optimiser: Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected).
+ *
+ * Inputs:  features  V^ = V e^{-i arg V_0} / |V| as (Re, Im) pairs (the Eq. 2
+ *          NLL depends on V only through these);  targets t = ln(1 + NLL -
+ *          min NLL).
+ *
+ * All array arguments are device pointers (FP32 unless stated) on the
+ * object's device; every call orders its work on the object's stream and
+ * waits for it before returning.  Errors: PWA_E_INVAL for bad sizes or null
+ * pointers, PWA_E_NOMEM, PWA_E_HIP.
+ * ------------------------------------------------------------------------ */
+typedef struct pwa_mlp pwa_mlp;
+
+/* Number of FP32 parameters of an in -> hidden -> hidden -> 1 network (-1 if a size is < 1). */
+int64_t pwa_mlp_param_count(int32_t in, int32_t hidden);
+
+/* Create a network on `device` (parameters zero; set them with
+ * pwa_mlp_set_params).  in 1..128, hidden 1..4096; max_batch 1..65536 rows
+ * bounds the training batch and the rows one inference pass holds.
+ * `stream`: hipStream_t or NULL (owned). */
+pwa_status pwa_mlp_create(pwa_mlp **out, int device, int32_t in, int32_t hidden, int32_t max_batch,
+                          void *stream);
+pwa_status pwa_mlp_destroy(pwa_mlp *m);
+
+/* Copy all parameters in (host or device memory per `where`); resets the
+ * Adam moments and step count. */
+pwa_status pwa_mlp_set_params(pwa_mlp *m, const float *P, pwa_where where);
+pwa_status pwa_mlp_get_params(pwa_mlp *m, float *P, pwa_where where);
+
+/* X [n][2k] = canonical features of V [n][2k] (FP64, interleaved complex);
+ * 2k must equal the input width.  A zero vector gives zero features. */
+pwa_status pwa_mlp_features(pwa_mlp *m, const double *V, int64_t n, int32_t k, float *X);
+
+/* t[n] = ln(1 + NLL - min NLL) from nll[n] (FP64); non-finite NLL values get
+ * the largest finite target + 1. */
+pwa_status pwa_mlp_targets(pwa_mlp *m, const double *nll, int64_t n, float *t);
+
+/* y[n] = network output for the rows of X [n][in]. */
+pwa_status pwa_mlp_predict(pwa_mlp *m, const float *X, int64_t n, float *y);
+
+/* One forward and backward pass over B <= max_batch rows without an update:
+ * *loss (host) = mean squared error, G = its gradient (layout of the
+ * parameters). */
+pwa_status pwa_mlp_loss_grad(pwa_mlp *m, const float *X, const float *t, int32_t B, float *loss, float *G);
+
+/* nsteps Adam steps with learning rate lr; step s uses the rows
+ * perm[s * batch .. s * batch + batch - 1] of X [n][in] and t[n] (perm: int32
+ * device array of nsteps * batch entries in [0, n); the random order is the
+ * caller's).  One step (gather, forward, backward, Adam) is captured in a HIP
+ * graph and replayed.  loss_hist (device, nsteps floats, or NULL) receives
+ * each step's batch loss; avg_ms (host, optional) the time per step.
+ * PWA_E_INVAL after the run if some perm entry was out of range (row 0 was
+ * used in its place). */
+pwa_status pwa_mlp_train(pwa_mlp *m, const float *X, const float *t, int64_t n, const int32_t *perm,
+                         int32_t batch, int32_t nsteps, float lr, float *loss_hist, double *avg_ms);
+
+/* idx[k] = indices of the k smallest of keys[n], ascending (ties by index,
+ * NaN counts as +inf); 1 <= k <= 2048, k <= n < 2^31. */
+pwa_status pwa_mlp_select(pwa_mlp *m, const float *keys, int64_t n, int32_t k, int32_t *idx);
+
+const char *pwa_mlp_last_error(const pwa_mlp *m);
+
 #ifdef __cplusplus
 }
 #endif

@@ -30,6 +30,9 @@ EXPORTS = [
     "pwa_set_stream_cfg", "pwa_autotune", "pwa_batch_kernel_time",
     "pwa_multi_create", "pwa_multi_destroy", "pwa_multi_eval", "pwa_multi_reset", "pwa_multi_step",
     "pwa_multi_get", "pwa_multi_autotune", "pwa_multi_last_error", "pwa_batch_fit",
+    "pwa_mlp_param_count", "pwa_mlp_create", "pwa_mlp_destroy", "pwa_mlp_set_params", "pwa_mlp_get_params",
+    "pwa_mlp_features", "pwa_mlp_targets", "pwa_mlp_predict", "pwa_mlp_loss_grad", "pwa_mlp_train",
+    "pwa_mlp_select", "pwa_mlp_last_error",
 ]
 
 
@@ -118,6 +121,16 @@ def load(path: str = LIB_PATH):
         "pwa_multi_step": [P, I32, ctypes.POINTER(D)],
         "pwa_multi_get": [P, P, P, P, P],
         "pwa_multi_autotune": [P, I32, ctypes.POINTER(I64), ctypes.POINTER(I32), ctypes.POINTER(D)],
+        "pwa_mlp_create": [ctypes.POINTER(P), ctypes.c_int, I32, I32, I32, P],
+        "pwa_mlp_destroy": [P],
+        "pwa_mlp_set_params": [P, P, ctypes.c_int],
+        "pwa_mlp_get_params": [P, P, ctypes.c_int],
+        "pwa_mlp_features": [P, P, I64, I32, P],
+        "pwa_mlp_targets": [P, P, I64, P],
+        "pwa_mlp_predict": [P, P, I64, P],
+        "pwa_mlp_loss_grad": [P, P, P, I32, ctypes.POINTER(ctypes.c_float), P],
+        "pwa_mlp_train": [P, P, P, I64, P, I32, I32, ctypes.c_float, P, ctypes.POINTER(D)],
+        "pwa_mlp_select": [P, P, I64, I32, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -127,6 +140,10 @@ def load(path: str = LIB_PATH):
     lib.pwa_last_error.restype = ctypes.c_char_p
     lib.pwa_multi_last_error.argtypes = [P]
     lib.pwa_multi_last_error.restype = ctypes.c_char_p
+    lib.pwa_mlp_last_error.argtypes = [P]
+    lib.pwa_mlp_last_error.restype = ctypes.c_char_p
+    lib.pwa_mlp_param_count.argtypes = [I32, I32]
+    lib.pwa_mlp_param_count.restype = I64
     _lib = lib
     return lib
 
@@ -438,3 +455,140 @@ class MultiFit:
             self.close()
         except Exception:
             pass
+
+
+class Mlp:
+    """Surrogate network in -> hidden -> hidden -> 1 on one GPU (pwa_mlp).
+
+    Array arguments are torch CUDA tensors (the library reads and writes them in
+    place); work is ordered after the caller's current PyTorch stream and the
+    calls return when it has finished.
+    """
+
+    def __init__(self, n_in: int, hidden: int = 256, max_batch: int = 8192, device: int = 0):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        self.n_in, self.hidden, self.max_batch = int(n_in), int(hidden), int(max_batch)
+        self.device = torch.device("cuda", device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        h = ctypes.c_void_p()
+        self.h = None
+        self._check(self.lib.pwa_mlp_create(ctypes.byref(h), device, self.n_in, self.hidden, self.max_batch,
+                                            ctypes.c_void_p(int(self.stream.cuda_stream))), None)
+        self.h = h
+        self.nparams = int(self.lib.pwa_mlp_param_count(self.n_in, self.hidden))
+
+    def _check(self, status: int, h=-1):
+        if status == OK:
+            return
+        msg = self.lib.pwa_mlp_last_error(self.h if h == -1 else h)
+        msg = msg.decode() if msg else ""
+        raise PwaError(status, msg)
+
+    def _dev(self, t, dtype, shape=None, name="array"):
+        torch = self.torch
+        if not (torch.is_tensor(t) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+            raise TypeError(f"{name} must be a contiguous CUDA tensor of {dtype}")
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} must have shape {tuple(shape)}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _sync_in(self):
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+
+    def set_params(self, P):
+        """P: host numpy float32 [nparams] or a CUDA float32 tensor; resets Adam."""
+        if self.torch.is_tensor(P):
+            self._sync_in()
+            self._check(self.lib.pwa_mlp_set_params(self.h, self._dev(P, self.torch.float32, (self.nparams,)),
+                                                    DEVICE))
+        else:
+            p = np.ascontiguousarray(P, dtype=np.float32)
+            if p.shape != (self.nparams,):
+                raise ValueError(f"P must have shape ({self.nparams},)")
+            self._check(self.lib.pwa_mlp_set_params(self.h, _ptr(p), HOST))
+
+    def get_params(self) -> np.ndarray:
+        p = np.empty(self.nparams, dtype=np.float32)
+        self._check(self.lib.pwa_mlp_get_params(self.h, _ptr(p), HOST))
+        return p
+
+    def features(self, V):
+        """V: CUDA float64 [n, 2k] (interleaved complex) -> CUDA float32 [n, 2k]."""
+        torch = self.torch
+        n, kk = V.shape
+        X = torch.empty((n, kk), dtype=torch.float32, device=self.device)
+        self._sync_in()
+        self._check(self.lib.pwa_mlp_features(self.h, self._dev(V, torch.float64, name="V"), n, kk // 2,
+                                              ctypes.c_void_p(X.data_ptr())))
+        return X
+
+    def targets(self, nll):
+        torch = self.torch
+        t = torch.empty(nll.shape[0], dtype=torch.float32, device=self.device)
+        self._sync_in()
+        self._check(self.lib.pwa_mlp_targets(self.h, self._dev(nll, torch.float64, name="nll"), nll.shape[0],
+                                             ctypes.c_void_p(t.data_ptr())))
+        return t
+
+    def predict(self, X):
+        torch = self.torch
+        n = X.shape[0]
+        y = torch.empty(n, dtype=torch.float32, device=self.device)
+        self._sync_in()
+        self._check(self.lib.pwa_mlp_predict(self.h, self._dev(X, torch.float32, (n, self.n_in), "X"), n,
+                                             ctypes.c_void_p(y.data_ptr())))
+        return y
+
+    def loss_grad(self, X, t):
+        torch = self.torch
+        B = X.shape[0]
+        G = torch.empty(self.nparams, dtype=torch.float32, device=self.device)
+        loss = ctypes.c_float()
+        self._sync_in()
+        self._check(self.lib.pwa_mlp_loss_grad(self.h, self._dev(X, torch.float32, (B, self.n_in), "X"),
+                                               self._dev(t, torch.float32, (B,), "t"), B, ctypes.byref(loss),
+                                               ctypes.c_void_p(G.data_ptr())))
+        return float(loss.value), G
+
+    def train(self, X, t, perm, batch: int, lr: float = 1e-3):
+        """Adam steps over the rows perm[s * batch: (s + 1) * batch] for every s;
+        perm: CUDA int32 tensor.  Returns (per-step losses, ms per step)."""
+        torch = self.torch
+        n = X.shape[0]
+        nsteps = perm.numel() // batch
+        hist = torch.empty(max(nsteps, 1), dtype=torch.float32, device=self.device)
+        ms = ctypes.c_double()
+        self._sync_in()
+        self._check(self.lib.pwa_mlp_train(self.h, self._dev(X, torch.float32, (n, self.n_in), "X"),
+                                           self._dev(t, torch.float32, (n,), "t"),
+                                           n, self._dev(perm, torch.int32, name="perm"), int(batch), int(nsteps),
+                                           float(lr), ctypes.c_void_p(hist.data_ptr()), ctypes.byref(ms)))
+        return hist[:nsteps], ms.value
+
+    def select(self, keys, k: int):
+        """Indices (CUDA int32 [k]) of the k smallest keys, ascending."""
+        torch = self.torch
+        idx = torch.empty(k, dtype=torch.int32, device=self.device)
+        self._sync_in()
+        self._check(self.lib.pwa_mlp_select(self.h, self._dev(keys, torch.float32, name="keys"), keys.shape[0],
+                                            int(k), ctypes.c_void_p(idx.data_ptr())))
+        return idx
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.pwa_mlp_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -185,7 +185,7 @@ struct MlpBuffers {
     float *dZ1, *dZ2;                 // their gradients
     float *y, *dy, *lrow, *loss;      // outputs, output gradient, per-row loss, mean loss
     float *Xb, *tb;                   // gathered mini-batch features and targets
-    int *step, *batch;                // Adam step count, mini-batch index (device)
+    int *step, *batch, *bad;          // Adam step count, mini-batch index, bad-index flag (device)
 };
 
 int64_t mlp_param_count(int in, int hidden);
@@ -193,13 +193,22 @@ int64_t mlp_param_count(int in, int hidden);
 hipError_t mlp_features(const double *V, int64_t n, int k, float *X, hipStream_t s);
 // Targets ln(1 + NLL - min NLL) (one block).
 hipError_t mlp_targets(const double *nll, int64_t n, float *t, hipStream_t s);
-// Forward pass over B rows of Xb (outputs in m.y); with train, loss and gradient into m.G.
-hipError_t mlp_pass(const MlpBuffers &m, int B, const float *Xb, const float *tb, bool train, hipStream_t s);
-hipError_t mlp_adam(const MlpBuffers &m, float lr, hipStream_t s);
-hipError_t mlp_gather(const MlpBuffers &m, const float *X, const float *t, const int *perm, int B, hipStream_t s);
-hipError_t mlp_step_inc(const MlpBuffers &m, int nbatches, hipStream_t s);
+// Forward pass over B rows of Xb into y; with train, the loss (hist[*m.batch]
+// too when hist is set) and the gradient of the summed squared error into m.G.
+hipError_t mlp_pass(const MlpBuffers &m, int B, const float *Xb, const float *tb, float *y, bool train, float *hist,
+                    hipStream_t s);
+hipError_t mlp_scale(const float *x, int64_t n, float scale, float *out, hipStream_t s);
+// Adam on m.P with gradient m.G * gscale; step count at m.step (not advanced here).
+hipError_t mlp_adam(const MlpBuffers &m, float gscale, float lr, hipStream_t s);
+// Rows perm[*m.batch * B + r] of X [n][in] and t into m.Xb, m.tb (*m.bad set
+// for an index outside [0, n)).
+hipError_t mlp_gather(const MlpBuffers &m, const float *X, const float *t, int64_t n, const int *perm, int B,
+                      hipStream_t s);
+hipError_t mlp_step_inc(const MlpBuffers &m, hipStream_t s);
+hipError_t mlp_set_int(int *p, int v, hipStream_t s);
 // Indices of the k smallest keys (ties by index; NaN counts as +inf), ascending.
-size_t topk_scratch(int n, int k);
-hipError_t mlp_topk(const float *keys, int n, int k, float *sk, int *si, int *out, hipStream_t s);
+int topk_chunk();
+size_t topk_scratch(int64_t n, int k);
+hipError_t mlp_topk(const float *keys, int64_t n, int k, float *sk[2], int *si[2], int *out, hipStream_t s);
 
 }  // namespace pwa

@@ -36,7 +36,7 @@ X_LO, X_HI = -1.0, 1.0          # cos(theta) range
 
 # Random streams, one per independent draw, so that changing one size never
 # shifts another draw.
-_S_WAVES, _S_VTRUE, _S_MC, _S_DATA, _S_VEVAL, _S_PILOT = range(6)
+_S_WAVES, _S_VTRUE, _S_MC, _S_DATA, _S_VEVAL, _S_PILOT, _S_NET = range(7)
 
 CHUNK = 1 << 18
 
@@ -320,14 +320,6 @@ def multifit_table(nfits: int = 64, seed: int = 0):
     return [(int(a), int(b), int(5 * a)) for a, b in zip(nd, ks)]
 
 
-def canonical(v: np.ndarray) -> np.ndarray:
-    """Representative of V modulo a complex factor: V_0 real > 0 and |V| = 1."""
-    v = np.asarray(v)
-    ph = np.exp(-1j * np.angle(v[..., :1]))
-    u = v * ph
-    return u / np.linalg.norm(u, axis=-1, keepdims=True)
-
-
 def gaussian_integer_amplitudes(g: np.random.Generator, n: int, k: int, bound: int = 4,
                                 dtype=np.complex64) -> np.ndarray:
     """Amplitudes with integer real and imaginary parts in [-bound, bound]."""
@@ -339,3 +331,29 @@ def gaussian_integer_amplitudes(g: np.random.Generator, n: int, k: int, bound: i
 def random_amplitudes(g: np.random.Generator, n: int, k: int, dtype=np.complex64) -> np.ndarray:
     """Unstructured complex normal amplitudes (for shape and edge-case tests)."""
     return (g.standard_normal((n, k)) + 1j * g.standard_normal((n, k))).astype(dtype)
+
+
+# --------------------------------------------------------- surrogate inputs
+def mlp_init(n_in: int, hidden: int, seed: int = 0) -> np.ndarray:
+    """Initial parameters of an n_in -> hidden -> hidden -> 1 network, FP32, in the
+    layout [W1 (hidden x n_in) | b1 | W2 (hidden x hidden) | b2 | w3 | b3].
+
+    Every weight and bias of a layer with fan-in f is uniform in [-1/sqrt(f),
+    1/sqrt(f)] (the default initialisation of a PyTorch linear layer).
+    """
+    g = rng_for(4, seed, _S_NET)
+    parts = []
+    for fan_in, shape in ((n_in, (hidden, n_in)), (n_in, (hidden,)), (hidden, (hidden, hidden)),
+                          (hidden, (hidden,)), (hidden, (hidden,)), (hidden, (1,))):
+        b = 1.0 / np.sqrt(fan_in)
+        parts.append(g.uniform(-b, b, shape).ravel())
+    return np.concatenate(parts).astype(np.float32)
+
+
+def permutations(n: int, epochs: int, batch: int, seed: int = 0) -> np.ndarray:
+    """Mini-batch order for `epochs` passes over n rows: each epoch a fresh
+    random permutation cut into floor(n / batch) batches (the remainder is
+    left out of that epoch).  int32, epochs * floor(n / batch) * batch entries."""
+    g = rng_for(4, seed, _S_NET * 1000 + 1)
+    per = (n // batch) * batch
+    return np.concatenate([g.permutation(n)[:per] for _ in range(epochs)]).astype(np.int32)

@@ -37,3 +37,20 @@ def test_errors_without_gpu_or_context():
     assert lib.pwa_destroy(None) == 0
     assert lib.pwa_set_mc_mode(None, 0, 0) == 1
     assert b"null" in lib.pwa_last_error(None)
+
+
+def test_mlp_host_side_checks():
+    """Parameter count of the 32 -> 256 -> 256 -> 1 network and argument checks
+    that need no device."""
+    if not os.path.exists(pwa.LIB_PATH):
+        pytest.skip("libpwa.so not built")
+    import ctypes
+    lib = pwa.load()
+    assert lib.pwa_mlp_param_count(32, 256) == 32 * 256 + 256 + 256 * 256 + 256 + 256 + 1 == 74497
+    assert lib.pwa_mlp_param_count(0, 256) == -1
+    assert lib.pwa_mlp_create(None, 0, 32, 256, 64, None) == 1
+    h = ctypes.c_void_p()
+    assert lib.pwa_mlp_create(ctypes.byref(h), 0, 0, 256, 64, None) == 1
+    assert b"shape" in lib.pwa_mlp_last_error(None)
+    assert lib.pwa_mlp_destroy(None) == 0
+    assert lib.pwa_mlp_set_params(None, None, 0) == 1

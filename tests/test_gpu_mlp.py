@@ -1,0 +1,251 @@
+"""GPU parity of the surrogate-network kernels against the FP64 network oracle,
+and what the trained network gains in multi-start fits.
+
+Tolerance.  The oracle rounds to FP16 exactly where the kernels do and keeps
+everything else in FP64.  Errors are scaled by S, the sum of the absolute
+values of the terms that make an output up (for y_b: sum_j |h_bj w_j| + |b3|;
+for a gradient entry the same products in absolute value, e.g. |dZ2|^T |H1| / B
+for dW2).  Two effects remain:
+  - FP32 accumulation and FP32 GELU: of order 1e-7 S, so the median over an
+    output block must stay below 2e-6;
+  - FP16 rounding decisions that an upstream FP32-vs-FP64 difference tips the
+    other way: each moves one operand element by one FP16 ulp, 2^-11 of one
+    term, and they are rare, so they only shape the tail: the 99th percentile
+    must stay below 5e-5 and the maximum below 1e-4 (a few such changes on
+    the largest terms).
+A wrong operand precision (BF16 instead of FP16, 2^-8), a missing term or a
+GELU of the wrong form moves the median by 1e-5 or more.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle.mlp as OM
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+@pytest.fixture(scope="module")
+def pwa():
+    import paper_1108_5882_amd as p
+    return p
+
+
+def _scales(P, X, t, n_in, hidden):
+    """Absolute-term sums of the output and of every gradient entry (oracle values, rounded)."""
+    r = OM.f16
+    W1, b1, W2, b2, w3, b3 = OM.unpack(P, n_in, hidden)
+    a = OM.forward(P, X, n_in, hidden, rounding=True)
+    B = X.shape[0]
+    aH2, aw3, aH1, aX = np.abs(r(a["H2"])), np.abs(r(w3)), np.abs(r(a["H1"])), np.abs(r(a["X"]))
+    s_y = aH2 @ aw3 + abs(b3[0])
+    dy = np.abs(2.0 * (a["y"] - t))
+    dZ2 = np.outer(dy, aw3) * np.abs(OM.gelu_d(a["Z2"]))
+    dZ1 = (np.abs(r(dZ2)) @ np.abs(r(W2))) * np.abs(OM.gelu_d(a["Z1"]))
+    S = OM.pack(np.abs(r(dZ1)).T @ aX, dZ1.sum(0), np.abs(r(dZ2)).T @ aH1, dZ2.sum(0), aH2.T @ dy,
+                np.array([dy.sum()])) / B
+    return s_y, S
+
+
+def _check(label, err, scale):
+    e = np.abs(err) / scale
+    med, p99, mx = np.median(e), np.percentile(e, 99), e.max()
+    _say(f"  {label}: scaled error median {med:.1e}, p99 {p99:.1e}, max {mx:.1e}")
+    assert med < 2e-6 and p99 < 5e-5 and mx < 1e-4, label
+
+
+def _blocks(n_in, hidden):
+    sizes = [hidden * n_in, hidden, hidden * hidden, hidden, hidden, 1]
+    names = ["W1", "b1", "W2", "b2", "w3", "b3"]
+    out, o = [], 0
+    for nm, sz in zip(names, sizes):
+        out.append((nm, slice(o, o + sz)))
+        o += sz
+    return out
+
+
+@pytest.mark.parametrize("B", [1, 300, 1024])
+def test_forward_and_gradient_match_oracle(pwa, torch, B):
+    n_in, hidden = 32, 256
+    _say(f"case mlp loss_grad B={B}")
+    P = synth.mlp_init(n_in, hidden, seed=B)
+    g = np.random.default_rng(B)
+    X = OM.features(synth.draw_v(g, B, n_in // 2)).astype(np.float32)
+    t = g.uniform(0.0, 3.0, B).astype(np.float32)
+    with pwa.Mlp(n_in, hidden, max_batch=1024) as m:
+        m.set_params(P)
+        assert np.array_equal(m.get_params(), P)
+        Xd = torch.from_numpy(X).cuda()
+        td = torch.from_numpy(t).cuda()
+        y = m.predict(Xd).cpu().numpy()
+        loss, G = m.loss_grad(Xd, td)
+        G = G.cpu().numpy()
+    a = OM.forward(P, X, n_in, hidden, rounding=True)
+    l_or, G_or = OM.loss_grad(P, X, t, n_in, hidden, rounding=True)
+    sy, S = _scales(P.astype(np.float64), X.astype(np.float64), t.astype(np.float64), n_in, hidden)
+    _say(f"  loss {loss:.7f} vs {l_or:.7f}")
+    _check("y", y - a["y"], sy)
+    assert abs(loss - l_or) <= 1e-4 * np.mean(2 * np.abs(a["y"] - t) * sy) + 1e-6 * l_or
+    for nm, sl in _blocks(n_in, hidden):
+        _check("d" + nm, G[sl] - G_or[sl], S[sl] + 1e-30)
+
+
+def test_predict_in_chunks_and_ragged(pwa, torch):
+    """Inference over more rows than one pass holds (chunked) equals row-by-row passes."""
+    n_in, hidden = 32, 256
+    P = synth.mlp_init(n_in, hidden, seed=3)
+    g = np.random.default_rng(9)
+    X = OM.features(synth.draw_v(g, 2500, 16)).astype(np.float32)
+    with pwa.Mlp(n_in, hidden, max_batch=1000) as m:
+        m.set_params(P)
+        Xd = torch.from_numpy(X).cuda()
+        y = m.predict(Xd).cpu().numpy()
+        y2 = np.concatenate([m.predict(Xd[i:i + 7]).cpu().numpy() for i in range(0, 2500, 7)])
+        assert m.predict(Xd[:0]).shape == (0,)
+    a = OM.forward(P, X, n_in, hidden, rounding=True)
+    sy, _ = _scales(P.astype(np.float64), X.astype(np.float64), np.zeros(2500), n_in, hidden)
+    _check("y (chunked)", y - a["y"], sy)
+    assert np.array_equal(y, y2)              # a row's result does not depend on its batch
+
+
+def test_adam_steps_match_oracle(pwa, torch):
+    """Two training steps (same batch) against the oracle's Adam from the kernel's own gradients."""
+    n_in, hidden, B = 32, 256, 512
+    P0 = synth.mlp_init(n_in, hidden, seed=11)
+    g = np.random.default_rng(11)
+    X = OM.features(synth.draw_v(g, B, 16)).astype(np.float32)
+    t = g.uniform(0, 3, B).astype(np.float32)
+    lr = 1e-3
+    with pwa.Mlp(n_in, hidden, max_batch=B) as m:
+        m.set_params(P0)
+        Xd, td = torch.from_numpy(X).cuda(), torch.from_numpy(t).cuda()
+        perm = torch.arange(B, dtype=torch.int32, device="cuda")
+        _, G0 = m.loss_grad(Xd, td)
+        losses, _ = m.train(Xd, td, perm, B, lr)
+        P1 = m.get_params()
+        _, G1 = m.loss_grad(Xd, td)
+        m.train(Xd, td, perm, B, lr)
+        P2 = m.get_params()
+        # bad permutation entries are reported, not read
+        bad = torch.tensor([0, B + 5], dtype=torch.int32, device="cuda")
+        with pytest.raises(pwa.PwaError):
+            m.train(Xd, td, bad, 2, lr)
+    G0, G1 = G0.cpu().numpy().astype(np.float64), G1.cpu().numpy().astype(np.float64)
+    Q1, mm, vv = OM.adam(P0, G0, 0.0, 0.0, 0, lr)
+    Q2, _, _ = OM.adam(P1, G1, mm, vv, 1, lr)
+    e1 = np.max(np.abs(P1 - Q1))
+    e2 = np.max(np.abs(P2 - Q2))
+    _say(f"case mlp adam: step 1 max |dP| {e1:.2e}, step 2 {e2:.2e}; loss {losses[0].item():.5f}")
+    # FP32 parameters: the update itself (<= lr) is exact to FP32 rounding of P and of the step
+    assert e1 < 2e-7 * (1 + np.abs(P0).max()) and e2 < 2e-7 * (1 + np.abs(P0).max())
+    l_or, _ = OM.loss_grad(P0, X, t, n_in, hidden)
+    assert abs(losses[0].item() - l_or) < 1e-5 * l_or
+
+
+def test_features_targets_select(pwa, torch):
+    g = np.random.default_rng(12)
+    V = synth.draw_v(g, 5000, 16)
+    V[3] = 0.0                                           # zero vector: zero features
+    Vi = np.empty((V.shape[0], 32))
+    Vi[:, 0::2], Vi[:, 1::2] = V.real, V.imag
+    nll = g.normal(1000.0, 300.0, 5000)
+    nll[[5, 9]] = np.inf
+    with pwa.Mlp(32, 64, max_batch=256) as m:
+        X = m.features(torch.from_numpy(Vi).cuda()).cpu().numpy()
+        t = m.targets(torch.from_numpy(nll).cuda()).cpu().numpy()
+        Xo = OM.features(V).astype(np.float32)
+        Xo[3] = 0.0
+        assert np.all(X[:, 1] == 0.0)                        # Im of the first component is zero by construction
+        ulp = np.spacing(np.abs(Xo).astype(np.float32))
+        assert np.all(np.abs(X - Xo) <= ulp), np.max(np.abs(X - Xo) / ulp)
+        to = OM.targets(nll).astype(np.float32)
+        assert np.all(np.abs(t - to) <= np.spacing(np.abs(to).astype(np.float32)))
+        # top-k: ties by index, NaN as +inf; one chunk, several chunks, several rounds
+        for n, k in [(256, 256), (4096, 17), (100000, 256), (500000, 2048), (70001, 1)]:
+            keys = np.round(g.normal(size=n) * 50).astype(np.float32)      # many ties
+            keys[g.integers(0, n, 3)] = np.nan
+            idx = m.select(torch.from_numpy(keys).cuda(), k).cpu().numpy()
+            assert np.array_equal(idx, OM.topk(keys, k)), (n, k)
+        kd = torch.zeros(10, device="cuda")
+        for n, k in [(10, 0), (10, 11), (5000, 2049)]:
+            with pytest.raises(pwa.PwaError):
+                m.select(torch.zeros(n, device="cuda") if n != 10 else kd, k)
+
+
+def _spearman(a, b):
+    ra = np.argsort(np.argsort(a))
+    rb = np.argsort(np.argsort(b))
+    return np.corrcoef(ra, rb)[0, 1]
+
+
+@pytest.fixture(scope="module")
+def small_pipeline(pwa):
+    """K = 16 sample with 1% of the surrogate workload's events; 20000 training pairs."""
+    from paper_1108_5882_amd import surrogate
+    s = synth.make_sample(4, scale=0.01)
+    k = s.k
+    n_train, n_screen, top, batch, epochs = 20000, 20000, 64, 1000, 40
+    V_train = synth.eval_vectors(4, n_train, k, stream=1)
+    V_screen = synth.eval_vectors(4, n_screen, k, stream=2)
+    V_plain = synth.eval_vectors(4, top, k, stream=3)
+    perm = synth.permutations(n_train, epochs, batch, seed=1)
+    ctx = pwa.Context(0, "f32")
+    ctx.set_amplitudes("data", s.A_data)
+    ctx.set_amplitudes("mc", s.A_mc)
+    ctx.set_mc_mode("gram")
+    m = pwa.Mlp(2 * k, 256, max_batch=8192)
+    _say("case mlp pipeline (small)")
+    res = surrogate.multistart(ctx, m, V_train, V_screen, V_plain, perm, batch, iters=60, top=top,
+                               init=synth.mlp_init(2 * k, 256, seed=1))
+    V_hold = synth.eval_vectors(4, 2000, k, stream=4)
+    nll_hold = surrogate.exact_pairs(ctx, V_hold)
+    _, pred_hold = surrogate.screen(m, V_hold, 1)
+    yield dict(s=s, res=res, V_screen=V_screen, V_plain=V_plain, ctx=ctx, m=m, nll_hold=nll_hold,
+               pred_hold=pred_hold)
+    m.close()
+    ctx.close()
+
+
+def test_training_reduces_loss_and_generalises(small_pipeline):
+    d = small_pipeline
+    L = d["res"]["losses"]
+    first, last = L[:20].mean(), L[-20:].mean()
+    rho = _spearman(d["pred_hold"], d["nll_hold"])
+    _say(f"  loss {first:.4f} -> {last:.4f}; held-out rank correlation {rho:.3f}; "
+         f"{d['res']['ms_per_train_step']:.3f} ms/step")
+    assert last < 0.5 * first
+    assert rho > 0.6
+
+
+def test_screened_starts_beat_random_starts(small_pipeline):
+    """The network's picks start lower, and after the same refinement the best fit
+    is at least as low as the best of as many random starts."""
+    import oracle
+    d = small_pipeline
+    s, res = d["s"], d["res"]
+    sel = res["surrogate"]["sel"]
+    Vs, Vp = d["V_screen"][sel], d["V_plain"]
+    # exact NLL of the starts, by the oracle, on 16 of each
+    f_sel = np.array([oracle.nll_grad(s.A_data, s.A_mc, v)[0] for v in Vs[:16]])
+    f_pl = np.array([oracle.nll_grad(s.A_data, s.A_mc, v)[0] for v in Vp[:16]])
+    best_sel, best_pl = res["surrogate"]["nll"].min(), res["plain"]["nll"].min()
+    _say(f"  start NLL median: screened {np.median(f_sel):.1f}, random {np.median(f_pl):.1f}; "
+         f"after refinement best: screened {best_sel:.3f}, random {best_pl:.3f}; "
+         f"medians {np.median(res['surrogate']['nll']):.2f} / {np.median(res['plain']['nll']):.2f}; "
+         f"seconds {res['seconds']}")
+    assert np.median(f_sel) < np.median(f_pl)
+    assert np.median(res["surrogate"]["nll"]) < np.median(res["plain"]["nll"])
+    assert best_sel <= best_pl + 1e-6 * abs(best_pl)
