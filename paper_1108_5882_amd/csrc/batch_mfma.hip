@@ -52,7 +52,9 @@ __global__ __launch_bounds__(kThreads) void nll_batch_kernel(BatchArgs p) {
     constexpr int kVPerWave = 8 * CT;
     constexpr int K2 = 32 * KS;                 // padded real width
     constexpr int RS16 = K2 + 8;                // row stride (halfs) of the row-major FP16 planes
-    constexpr int RST = kTile + 4;              // row stride (bf16) of the transposed planes
+    constexpr int RST = kTile + 8;              // row stride (bf16) of the transposed planes (16-byte rows)
+    constexpr int kPairs = kTile * K2 / 2;      // float pairs of a tile
+    constexpr int kPer = (kPairs + kThreads - 1) / kThreads;
     __shared__ __attribute__((aligned(16))) _Float16 ah[kTile * RS16];
     __shared__ __attribute__((aligned(16))) _Float16 al[kTile * RS16];
     __shared__ __attribute__((aligned(16))) __bf16 bh[K2 * RST];
@@ -96,36 +98,56 @@ __global__ __launch_bounds__(kThreads) void nll_batch_kernel(BatchArgs p) {
     for (int g = 0; g < CT / 2; ++g) tsum[g] = 0.0;
 
     const int nreal = 2 * p.k;                      // real columns present in a row
-    for (int64_t t = tile0; t < tile1; ++t) {
-        // ---- stage the tile: FP16 (scaled) row-major planes and BF16 transposed planes
-        __syncthreads();
-        for (int c = tid; c < kTile * K2 / 2; c += kThreads) {
-            const int e = c / (K2 / 2), r = 2 * (c % (K2 / 2));
-            const int64_t row = t * kTile + e;
-            float x0 = 0.f, x1 = 0.f;
-            if (row < n && r < nreal) {
-                const float *src = A + 2 * (row * p.ld) + r;
-                x0 = src[0];
-                x1 = r + 1 < nreal ? src[1] : 0.f;
+    // The next tile's rows are loaded into registers while the current tile is
+    // computed; each thread holds kPer (re, im) pairs and one MC weight.
+    f2 xr[kPer];
+    float wr = 0.f;
+    auto load_tile = [&](int64_t t) {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int c = tid + i * kThreads;
+            xr[i] = f2{0.f, 0.f};
+            if (c < kPairs) {
+                const int e = c / (K2 / 2), r = 2 * (c % (K2 / 2));
+                const int64_t row = t * kTile + e;
+                if (row < n && r < nreal) xr[i] = *reinterpret_cast<const f2 *>(A + 2 * (row * p.ld) + r);
             }
-            const float s0 = p.ascale[r], s1 = p.ascale[r + 1];
-            const float y0 = x0 * s0, y1 = x1 * s1;
-            const _Float16 h0 = (_Float16)y0, h1 = (_Float16)y1;
-            ah[e * RS16 + r] = h0;
-            ah[e * RS16 + r + 1] = h1;
-            al[e * RS16 + r] = (_Float16)(y0 - (float)h0);
-            al[e * RS16 + r + 1] = (_Float16)(y1 - (float)h1);
-            const __bf16 g0 = (__bf16)x0, g1 = (__bf16)x1;
-            bh[r * RST + e] = g0;
-            bh[(r + 1) * RST + e] = g1;
-            bl[r * RST + e] = (__bf16)(x0 - (float)g0);
-            bl[(r + 1) * RST + e] = (__bf16)(x1 - (float)g1);
         }
         if (tid < kTile) {
             const int64_t row = t * kTile + tid;
-            wts[tid] = row < n ? (w ? w[row] : 1.f) : 0.f;
+            wr = row < n ? (w ? w[row] : 1.f) : 0.f;
         }
+    };
+    if (tile0 < tile1) load_tile(tile0);
+    for (int64_t t = tile0; t < tile1; ++t) {
+        // ---- stage the tile: FP16 (scaled) row-major planes and BF16 transposed
+        // planes; in the transposed planes event e sits at position
+        // 8 ((e mod 16) / 4) + (e mod 4) + 4 (e / 16), the adjoint's operand order,
+        // so that a lane reads its 8 values in one 16-byte access
         __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int c = tid + i * kThreads;
+            if (c < kPairs) {
+                const int e = c / (K2 / 2), r = 2 * (c % (K2 / 2));
+                const float x0 = xr[i][0], x1 = xr[i][1];
+                const float y0 = x0 * p.ascale[r], y1 = x1 * p.ascale[r + 1];
+                const _Float16 h0 = (_Float16)y0, h1 = (_Float16)y1;
+                ah[e * RS16 + r] = h0;
+                ah[e * RS16 + r + 1] = h1;
+                al[e * RS16 + r] = (_Float16)(y0 - (float)h0);
+                al[e * RS16 + r + 1] = (_Float16)(y1 - (float)h1);
+                const int pe = 8 * ((e & 15) >> 2) + (e & 3) + 4 * (e >> 4);
+                const __bf16 g0 = (__bf16)x0, g1 = (__bf16)x1;
+                bh[r * RST + pe] = g0;
+                bh[(r + 1) * RST + pe] = g1;
+                bl[r * RST + pe] = (__bf16)(x0 - (float)g0);
+                bl[(r + 1) * RST + pe] = (__bf16)(x1 - (float)g1);
+            }
+        }
+        if (tid < kTile) wts[tid] = wr;
+        __syncthreads();
+        if (t + 1 < tile1) load_tile(t + 1);
         if (v0 >= p.nv) continue;        // wave without vectors (last group)
 
         // ---- forward: Z[rt][ct] (rows: events 16 rt + 4q + e, column r16 of tile ct)
@@ -190,14 +212,8 @@ __global__ __launch_bounds__(kThreads) void nll_batch_kernel(BatchArgs p) {
 #pragma unroll
         for (int rt = 0; rt < 2 * KS; ++rt) {
             const int rr = 16 * rt + r16;
-            b8 b_h, b_l;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                b_h[e] = bh[rr * RST + 4 * q + e];
-                b_h[4 + e] = bh[rr * RST + 16 + 4 * q + e];
-                b_l[e] = bl[rr * RST + 4 * q + e];
-                b_l[4 + e] = bl[rr * RST + 16 + 4 * q + e];
-            }
+            const b8 b_h = *reinterpret_cast<const b8 *>(&bh[rr * RST + 8 * q]);
+            const b8 b_l = *reinterpret_cast<const b8 *>(&bl[rr * RST + 8 * q]);
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
                 D[ct][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uh[ct], b_h, D[ct][rt], 0, 0, 0);
@@ -248,8 +264,13 @@ __global__ __launch_bounds__(kThreads) void nll_batch_kernel(BatchArgs p) {
 // Per vector v (one block each): add the block partials of each segment in
 // block order, undo the per-vector scale t_v of the forward weights, and form
 // NLL and gradient (Eq. 2 or Eq. 3 form; streamed MC or the MC matrix).
+// The block partials of a segment are summed by G = 256 / pstride thread
+// groups (group g takes blocks g, g + G, ...; threads of a group take the
+// pstride values of a block, so each block's partial row is read contiguously),
+// then the G group sums are added in group order: the order is fixed.
 __global__ __launch_bounds__(256) void nll_batch_combine_kernel(BatchArgs p) {
     __shared__ double tot[2][1 + 2 * PWA_MAX_K];
+    __shared__ double grp[256];
     __shared__ double mv[2 * PWA_MAX_K];
     __shared__ double s_c;
     const int v = blockIdx.x, tid = threadIdx.x;
@@ -257,14 +278,23 @@ __global__ __launch_bounds__(256) void nll_batch_combine_kernel(BatchArgs p) {
     const int nblk = p.nb[0] + p.nb[1];
     const int k = p.k;
     const double *base = p.partials + (int64_t)v * nblk * pst;
-    for (int idx = tid; idx < 2 * pst; idx += 256) {
-        const int sg = idx / pst, cc = idx % pst;
+    const int G = 256 / pst, g = tid / pst, cc = tid % pst;
+    for (int sg = 0; sg < 2; ++sg) {
         const int b0 = sg ? p.nb[0] : 0, b1 = sg ? nblk : p.nb[0];
-        double s = 0.0;
-        for (int b = b0; b < b1; ++b) s += base[(int64_t)b * pst + cc];
-        tot[sg][cc] = s;
+        if (g < G) {
+            double s = 0.0;
+#pragma unroll 4
+            for (int b = b0 + g; b < b1; b += G) s += base[(int64_t)b * pst + cc];
+            grp[tid] = s;
+        }
+        __syncthreads();
+        if (tid < pst) {
+            double s = 0.0;
+            for (int h = 0; h < G; ++h) s += grp[h * pst + tid];
+            tot[sg][tid] = s;
+        }
+        __syncthreads();
     }
-    __syncthreads();
     const double tv = p.vscale[v];
     const double *V = p.V + (int64_t)v * p.vstride;
     if (p.gram) {

@@ -185,10 +185,14 @@ struct MlpBuffers {
     float *dZ1, *dZ2;                 // their gradients
     float *y, *dy, *lrow, *loss;      // outputs, output gradient, per-row loss, mean loss
     float *Xb, *tb;                   // gathered mini-batch features and targets
+    float *ws;                        // reduction workspace, mlp_workspace_floats(in, hidden) floats
     int *step, *batch, *bad;          // Adam step count, mini-batch index, bad-index flag (device)
 };
 
 int64_t mlp_param_count(int in, int hidden);
+inline int64_t mlp_workspace_floats(int in, int hidden) {
+    return 16 * (int64_t)hidden * (hidden > in ? hidden : in);
+}
 // Canonical features of n vectors (FP64, 2k doubles each) into X [n][2k] FP32.
 hipError_t mlp_features(const double *V, int64_t n, int k, float *X, hipStream_t s);
 // Targets ln(1 + NLL - min NLL) (one block).

@@ -31,9 +31,11 @@ __device__ __forceinline__ float ld_f(const T *p, int64_t i) { return (float)p[i
 
 // C[M x N] = sum_k fp16(A(m, k)) fp16(B(n, k)), FP32 accumulation.
 // A(m, k) = A[m lda + k] (TA false) or A[k lda + m] (TA true); same for B.
+// Split K: block z covers k in [z kc, (z + 1) kc) and writes its slice of the
+// sum to C + z M N (a workspace the split reduction then adds in z order).
 template <typename TAe, typename TBe, bool TA, bool TB>
 __global__ __launch_bounds__(kGT) void gemm_kernel(int M, int N, int K, const TAe *A, int lda,
-                                                   const TBe *B, int ldb, float *C, int ldc) {
+                                                   const TBe *B, int ldb, float *C, int ldc, int kc) {
     __shared__ __attribute__((aligned(16))) _Float16 as[64 * kGS];
     __shared__ __attribute__((aligned(16))) _Float16 bs[64 * kGS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -45,20 +47,22 @@ __global__ __launch_bounds__(kGT) void gemm_kernel(int M, int N, int K, const TA
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += kGK) {
+    const int kb = blockIdx.z * kc, ke = kb + kc < K ? kb + kc : K;
+    C += (int64_t)blockIdx.z * M * N;
+    for (int k0 = kb; k0 < ke; k0 += kGK) {
         __syncthreads();
         for (int idx = tid; idx < 64 * kGK; idx += kGT) {
             const int r = TA ? idx % 64 : idx / kGK, c = TA ? idx / 64 : idx % kGK;
             const int m = m0 + r, k = k0 + c;
             float va = 0.f;
-            if (m < M && k < K) va = TA ? ld_f(A, (int64_t)k * lda + m) : ld_f(A, (int64_t)m * lda + k);
+            if (m < M && k < ke) va = TA ? ld_f(A, (int64_t)k * lda + m) : ld_f(A, (int64_t)m * lda + k);
             as[r * kGS + c] = (_Float16)va;
         }
         for (int idx = tid; idx < 64 * kGK; idx += kGT) {
             const int r = TB ? idx % 64 : idx / kGK, c = TB ? idx / 64 : idx % kGK;
             const int n = n0 + r, k = k0 + c;
             float vb = 0.f;
-            if (n < N && k < K) vb = TB ? ld_f(B, (int64_t)k * ldb + n) : ld_f(B, (int64_t)n * ldb + k);
+            if (n < N && k < ke) vb = TB ? ld_f(B, (int64_t)k * ldb + n) : ld_f(B, (int64_t)n * ldb + k);
             bs[r * kGS + c] = (_Float16)vb;
         }
         __syncthreads();
@@ -84,11 +88,29 @@ __global__ __launch_bounds__(kGT) void gemm_kernel(int M, int N, int K, const TA
             }
 }
 
+// out[i] = sum_z part[z n + i], z = 0 .. S-1 in order.
+__global__ void reduce_slices_kernel(const float *part, int S, int64_t n, float *out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int z = 0; z < S; ++z) s += part[(int64_t)z * n + i];
+        out[i] = s;
+    }
+}
+
+// Plain launch (S = 1), or split K over S slices through the workspace ws
+// (S M N floats) and an ordered reduction; C must then be dense (ldc = N).
 template <typename TAe, typename TBe, bool TA, bool TB>
 hipError_t gemm(int M, int N, int K, const TAe *A, int lda, const TBe *B, int ldb, float *C, int ldc,
-                hipStream_t s) {
-    const dim3 grid((N + 63) / 64, (M + 63) / 64);
-    hipLaunchKernelGGL((gemm_kernel<TAe, TBe, TA, TB>), grid, dim3(kGT), 0, s, M, N, K, A, lda, B, ldb, C, ldc);
+                hipStream_t s, int S = 1, float *ws = nullptr) {
+    const int kc = S > 1 ? ((K + S - 1) / S + kGK - 1) / kGK * kGK : K;
+    const int z = S > 1 ? (K + kc - 1) / kc : 1;
+    const dim3 grid((N + 63) / 64, (M + 63) / 64, z);
+    hipLaunchKernelGGL((gemm_kernel<TAe, TBe, TA, TB>), grid, dim3(kGT), 0, s, M, N, K, A, lda, B, ldb,
+                       z > 1 ? ws : C, z > 1 ? N : ldc, kc);
+    if (z == 1) return hipGetLastError();
+    const int64_t n = (int64_t)M * N;
+    hipLaunchKernelGGL(reduce_slices_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0,
+                       s, ws, z, n, C);
     return hipGetLastError();
 }
 
@@ -143,54 +165,62 @@ __global__ __launch_bounds__(256) void head_kernel(const float *H, const float *
         dZ[(int64_t)b * Hn + j] = d * (float)(_Float16)w3[j] * gelu_d(Z[(int64_t)b * Hn + j]);
 }
 
-// Column sums with optional row weights: out[n] = sum_m w_m f(X[m][n]) with
-// f = identity or FP16 rounding (fixed order: each of kCsRows row groups of
-// a block sums its rows in order, then the groups are added in order).
-// One block per 64 columns.  With loss set, block 0 also forms the mean of
-// the per-row losses (*loss, and hist[*batch] when hist is set) and the sum
-// of the row weights (*wsum).
+// Column sums with optional row weights: part[z][n] = sum over the rows of
+// slice z of w_m f(X[m][n]), f = identity or FP16 rounding.  Block (x, z)
+// covers 64 columns and the rows [z rc, (z + 1) rc); within a block each of
+// kCsRows row groups sums its rows in order and the groups are added in
+// order, and the slices are added in order by reduce_slices_kernel, so the
+// result does not depend on scheduling.
 constexpr int kCsRows = 16;
 
 template <bool ROUND>
-__global__ __launch_bounds__(64 * kCsRows) void colsum_kernel(const float *X, const float *w, int M, int N,
-                                                              float *out, const float *lrow, float *loss,
-                                                              float *wsum, float *hist, const int *batch) {
-    __shared__ float part[kCsRows][64];
-    __shared__ float lpart[kCsRows][2];
+__global__ __launch_bounds__(64 * kCsRows) void colsum_kernel(const float *X, const float *w, int M, int N, int rc,
+                                                              float *part) {
+    __shared__ float acc[kCsRows][64];
     const int c = threadIdx.x & 63, rg = threadIdx.x >> 6;
     const int n = blockIdx.x * 64 + c;
+    const int m0 = blockIdx.y * rc, m1 = m0 + rc < M ? m0 + rc : M;
     float s = 0.f;
     if (n < N)
-        for (int m = rg; m < M; m += kCsRows) {
+        for (int m = m0 + rg; m < m1; m += kCsRows) {
             const float x = X[(int64_t)m * N + n];
             const float v = ROUND ? (float)(_Float16)x : x;
             s += w ? w[m] * v : v;
         }
-    part[rg][c] = s;
-    if (loss && blockIdx.x == 0 && c == 0) {
-        float l = 0.f, ws = 0.f;
-        for (int m = rg; m < M; m += kCsRows) {
-            l += lrow[m];
-            ws += w[m];
-        }
-        lpart[rg][0] = l;
-        lpart[rg][1] = ws;
-    }
+    acc[rg][c] = s;
     __syncthreads();
     if (rg == 0 && n < N) {
         float t = 0.f;
-        for (int g = 0; g < kCsRows; ++g) t += part[g][c];
-        out[n] = t;
+        for (int g = 0; g < kCsRows; ++g) t += acc[g][c];
+        part[(int64_t)blockIdx.y * N + n] = t;
     }
-    if (loss && blockIdx.x == 0 && threadIdx.x == 0) {
-        float l = 0.f, ws = 0.f;
-        for (int g = 0; g < kCsRows; ++g) {
-            l += lpart[g][0];
-            ws += lpart[g][1];
+}
+
+// db3 = sum_b dy_b and the mean of the per-row losses (also hist[*batch] when
+// hist is set): one block, strided per-thread sums, then a fixed-order tree.
+__global__ __launch_bounds__(1024) void head_sums_kernel(const float *dy, const float *lrow, int M, float *db3,
+                                                         float *loss, float *hist, const int *batch) {
+    __shared__ float a[1024], b[1024];
+    const int t = threadIdx.x;
+    float s = 0.f, l = 0.f;
+    for (int m = t; m < M; m += 1024) {
+        s += dy[m];
+        l += lrow[m];
+    }
+    a[t] = s;
+    b[t] = l;
+    __syncthreads();
+    for (int off = 512; off > 0; off >>= 1) {
+        if (t < off) {
+            a[t] += a[t + off];
+            b[t] += b[t + off];
         }
-        *loss = l / (float)M;
-        *wsum = ws;
-        if (hist) hist[*batch] = l / (float)M;
+        __syncthreads();
+    }
+    if (t == 0) {
+        *db3 = a[0];
+        *loss = b[0] / (float)M;
+        if (hist) hist[*batch] = b[0] / (float)M;
     }
 }
 
@@ -337,6 +367,23 @@ __global__ __launch_bounds__(1024) void topk_chunk_kernel(const float *keys, con
 }  // namespace
 
 // ------------------------------------------------------------------ host side
+namespace {
+
+// out[n] = sum_m w_m f(X[m][n]) through slices in the workspace ws (>= 16 N floats).
+template <bool ROUND>
+hipError_t colsum(const float *X, const float *w, int M, int N, float *out, float *ws, hipStream_t s) {
+    const int S = std::max(1, std::min(16, (M + 63) / 64));
+    const int rc = (M + S - 1) / S;
+    hipLaunchKernelGGL((colsum_kernel<ROUND>), dim3((N + 63) / 64, S), dim3(64 * kCsRows), 0, s, X, w, M, N, rc, ws);
+    hipLaunchKernelGGL(reduce_slices_kernel, dim3((N + 255) / 256), dim3(256), 0, s, ws, S, (int64_t)N, out);
+    return hipGetLastError();
+}
+
+// Slices for a split-K weight-gradient product over K = B rows.
+int ksplit(int K) { return std::max(1, std::min(16, K / 64)); }
+
+}  // namespace
+
 int64_t mlp_param_count(int in, int hidden) {
     return (int64_t)hidden * in + hidden + (int64_t)hidden * hidden + hidden + hidden + 1;
 }
@@ -372,19 +419,19 @@ hipError_t mlp_pass(const MlpBuffers &m, int B, const float *Xb, const float *tb
     hipLaunchKernelGGL(head_kernel, dim3(B), dim3(256), 0, s, m.H2, m.Z2, w3, b3, tb, y, m.dy, m.dZ2, m.lrow, H,
                        train ? 1 : 0);
     if (!train) return hipGetLastError();
-    // dw3_j = sum_b dy_b fp16(H2_bj), db3 = sum_b dy_b, loss = mean of the row losses
-    hipLaunchKernelGGL((colsum_kernel<true>), dim3((H + 63) / 64), dim3(64 * kCsRows), 0, s, m.H2, m.dy, B, H, gw3,
-                       m.lrow, m.loss, gb3, hist, m.batch);
+    // dw3_j = sum_b dy_b fp16(H2_bj); db3 = sum_b dy_b and the mean loss
+    if ((e = colsum<true>(m.H2, m.dy, B, H, gw3, m.ws, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(head_sums_kernel, dim3(1), dim3(1024), 0, s, m.dy, m.lrow, B, gb3, m.loss, hist, m.batch);
     // layer 2: dW2 = dZ2^T H1, db2 = column sums of dZ2, dZ1 = (dZ2 W2) GELU'(Z1)
-    if ((e = gemm<float, float, true, true>(H, H, B, m.dZ2, H, m.H1, H, gW2, H, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL((colsum_kernel<false>), dim3((H + 63) / 64), dim3(64 * kCsRows), 0, s, m.dZ2, nullptr, B, H,
-                       gb2, nullptr, nullptr, nullptr, nullptr, nullptr);
+    if ((e = gemm<float, float, true, true>(H, H, B, m.dZ2, H, m.H1, H, gW2, H, s, ksplit(B), m.ws)) != hipSuccess)
+        return e;
+    if ((e = colsum<false>(m.dZ2, nullptr, B, H, gb2, m.ws, s)) != hipSuccess) return e;
     if ((e = gemm<float, float, false, true>(B, H, H, m.dZ2, H, W2, H, m.dZ1, H, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(gelu_back_kernel, dim3(eb), dim3(256), 0, s, m.dZ1, m.Z1, (int64_t)B * H);
     // layer 1: dW1 = dZ1^T X, db1 = column sums of dZ1
-    if ((e = gemm<float, float, true, true>(H, in, B, m.dZ1, H, Xb, in, gW1, in, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL((colsum_kernel<false>), dim3((H + 63) / 64), dim3(64 * kCsRows), 0, s, m.dZ1, nullptr, B, H,
-                       gb1, nullptr, nullptr, nullptr, nullptr, nullptr);
+    if ((e = gemm<float, float, true, true>(H, in, B, m.dZ1, H, Xb, in, gW1, in, s, ksplit(B), m.ws)) != hipSuccess)
+        return e;
+    if ((e = colsum<false>(m.dZ1, nullptr, B, H, gb1, m.ws, s)) != hipSuccess) return e;
     return hipGetLastError();
 }
 

@@ -135,6 +135,7 @@ pwa_status pwa_mlp_create(pwa_mlp **out, int device, int32_t in, int32_t hidden,
         (st = alloc(m, &b.dZ2, act)) || (st = alloc(m, &b.y, max_batch)) || (st = alloc(m, &b.dy, max_batch)) ||
         (st = alloc(m, &b.lrow, max_batch)) || (st = alloc(m, &b.loss, 1)) ||
         (st = alloc(m, &b.Xb, (size_t)max_batch * in)) || (st = alloc(m, &b.tb, max_batch)) ||
+        (st = alloc(m, &b.ws, (size_t)mlp_workspace_floats(in, hidden))) ||
         (st = alloc(m, &ints, 4))) {
         g_lerr = m->err;
         pwa_mlp_destroy(m);
