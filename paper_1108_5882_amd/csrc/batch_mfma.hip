@@ -44,35 +44,45 @@ __device__ __forceinline__ int dpp_xor1(int x) {
 }
 __device__ __forceinline__ float xor1_f(float x) { return __int_as_float(dpp_xor1(__float_as_int(x))); }
 
-// Block b covers tiles [t0, t0 + kTilesPerBlock) of one segment for the
-// vectors of blockIdx.y; each wave takes VPW = 8 CT vectors (2 CT real
-// columns in CT column tiles: re and im of 16 vectors per tile pair).
+// Block b covers tiles [t0, t0 + kTilesPerBlock) of one segment (SEG: 0 data,
+// 1 MC) for the vectors of blockIdx.y; each wave takes VPW = 8 CT vectors
+// (2 CT real columns in CT column tiles: re and im of 16 vectors per tile
+// pair).  Lanes of vectors past nv compute on zero weights and are never
+// written out; only the last, partial tile of the data segment masks events
+// (an absent data row would give z = 0 and a non-finite z / I, while an absent
+// MC row has weight 0).
 template <int KS, int CT>
-__global__ __launch_bounds__(kThreads) void nll_batch_kernel(BatchArgs p) {
+struct BatchSmem {
+    static constexpr int K2 = 32 * KS;          // padded real width
+    static constexpr int RS16 = K2 + 8;         // row stride (halfs) of the row-major FP16 planes
+    static constexpr int RST = kTile + 8;       // row stride (bf16) of the transposed planes (16-byte rows)
+    _Float16 ah[kTile * RS16];
+    _Float16 al[kTile * RS16];
+    __bf16 bh[K2 * RST];
+    __bf16 bl[K2 * RST];
+    float wts[kTile];
+};
+
+template <int KS, int CT, int SEG>
+__device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT> &sm, int bseg) {
     constexpr int kVPerWave = 8 * CT;
-    constexpr int K2 = 32 * KS;                 // padded real width
-    constexpr int RS16 = K2 + 8;                // row stride (halfs) of the row-major FP16 planes
-    constexpr int RST = kTile + 8;              // row stride (bf16) of the transposed planes (16-byte rows)
+    constexpr int K2 = BatchSmem<KS, CT>::K2;
+    constexpr int RS16 = BatchSmem<KS, CT>::RS16;
+    constexpr int RST = BatchSmem<KS, CT>::RST;
     constexpr int kPairs = kTile * K2 / 2;      // float pairs of a tile
     constexpr int kPer = (kPairs + kThreads - 1) / kThreads;
-    __shared__ __attribute__((aligned(16))) _Float16 ah[kTile * RS16];
-    __shared__ __attribute__((aligned(16))) _Float16 al[kTile * RS16];
-    __shared__ __attribute__((aligned(16))) __bf16 bh[K2 * RST];
-    __shared__ __attribute__((aligned(16))) __bf16 bl[K2 * RST];
-    __shared__ float wts[kTile];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int q = lane >> 4, r16 = lane & 15;
-    const int seg = (int)blockIdx.x < p.nb[0] ? 0 : 1;
-    const int bseg = seg ? (int)blockIdx.x - p.nb[0] : (int)blockIdx.x;
-    const int64_t n = p.n[seg];
-    const float *A = p.A[seg];
-    const float *w = seg ? p.w : nullptr;
+    const int64_t n = p.n[SEG];
+    const float *A = p.A[SEG];
+    const float *w = SEG ? p.w : nullptr;
     const int64_t tile0 = (int64_t)bseg * kTilesPerBlock;
     const int64_t ntiles = (n + kTile - 1) / kTile;
     const int64_t tile1 = tile0 + kTilesPerBlock < ntiles ? tile0 + kTilesPerBlock : ntiles;
     const int vg = (int)blockIdx.y * kWaves + wave;          // this wave's vector group
     const int v0 = vg * kVPerWave;
+    const bool active = v0 < p.nv;                           // wave-uniform
 
     // forward weights of this wave's vectors, fragment order [hi/lo][ct][ks][lane]
     h8 wh[CT][KS], wl[CT][KS];
@@ -113,11 +123,61 @@ __global__ __launch_bounds__(kThreads) void nll_batch_kernel(BatchArgs p) {
                 if (row < n && r < nreal) xr[i] = *reinterpret_cast<const f2 *>(A + 2 * (row * p.ld) + r);
             }
         }
-        if (tid < kTile) {
+        if (SEG && tid < kTile) {
             const int64_t row = t * kTile + tid;
             wr = row < n ? (w ? w[row] : 1.f) : 0.f;
         }
     };
+
+    // epilogue of one tile: per (event, vector) I, log2 I (data) or w I (MC),
+    // and U = z / I (data) or w z (MC), split into BF16 hi/lo in the adjoint's
+    // operand order (slot 4 rt + e holds event 16 rt + 4 q + e)
+    auto epilogue = [&](const f4 (&Z)[2][CT], b8 (&uh)[CT], b8 (&ul)[CT], int nvalid) {
+        float wv[8];
+        if (SEG) {
+            const f4 w0 = *reinterpret_cast<const f4 *>(&sm.wts[4 * q]);
+            const f4 w1 = *reinterpret_cast<const f4 *>(&sm.wts[16 + 4 * q]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                wv[e] = w0[e];
+                wv[4 + e] = w1[e];
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < CT / 2; ++g) {
+            float ts = 0.f;
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int slot = 4 * rt + e;
+                    const float zr = Z[rt][2 * g][e], zi = Z[rt][2 * g + 1][e];
+                    const float I = fmaf(zr, zr, zi * zi);
+                    float ur, ui;
+                    if (SEG == 0) {
+                        if (nvalid < kTile && 16 * rt + 4 * q + e >= nvalid) {
+                            ur = ui = 0.f;
+                        } else {
+                            ts += __log2f(I);
+                            const float rI = __builtin_amdgcn_rcpf(I);
+                            ur = zr * rI;
+                            ui = zi * rI;
+                        }
+                    } else {
+                        ts = fmaf(wv[slot], I, ts);
+                        ur = wv[slot] * zr;
+                        ui = wv[slot] * zi;
+                    }
+                    const __bf16 hr = (__bf16)ur, hi_ = (__bf16)ui;
+                    uh[2 * g][slot] = hr;
+                    uh[2 * g + 1][slot] = hi_;
+                    ul[2 * g][slot] = (__bf16)(ur - (float)hr);
+                    ul[2 * g + 1][slot] = (__bf16)(ui - (float)hi_);
+                }
+            tsum[g] += (double)ts;
+        }
+    };
+
     if (tile0 < tile1) load_tile(tile0);
     for (int64_t t = tile0; t < tile1; ++t) {
         // ---- stage the tile: FP16 (scaled) row-major planes and BF16 transposed
@@ -133,22 +193,22 @@ __global__ __launch_bounds__(kThreads) void nll_batch_kernel(BatchArgs p) {
                 const float x0 = xr[i][0], x1 = xr[i][1];
                 const float y0 = x0 * p.ascale[r], y1 = x1 * p.ascale[r + 1];
                 const _Float16 h0 = (_Float16)y0, h1 = (_Float16)y1;
-                ah[e * RS16 + r] = h0;
-                ah[e * RS16 + r + 1] = h1;
-                al[e * RS16 + r] = (_Float16)(y0 - (float)h0);
-                al[e * RS16 + r + 1] = (_Float16)(y1 - (float)h1);
+                sm.ah[e * RS16 + r] = h0;
+                sm.ah[e * RS16 + r + 1] = h1;
+                sm.al[e * RS16 + r] = (_Float16)(y0 - (float)h0);
+                sm.al[e * RS16 + r + 1] = (_Float16)(y1 - (float)h1);
                 const int pe = 8 * ((e & 15) >> 2) + (e & 3) + 4 * (e >> 4);
                 const __bf16 g0 = (__bf16)x0, g1 = (__bf16)x1;
-                bh[r * RST + pe] = g0;
-                bh[(r + 1) * RST + pe] = g1;
-                bl[r * RST + pe] = (__bf16)(x0 - (float)g0);
-                bl[(r + 1) * RST + pe] = (__bf16)(x1 - (float)g1);
+                sm.bh[r * RST + pe] = g0;
+                sm.bh[(r + 1) * RST + pe] = g1;
+                sm.bl[r * RST + pe] = (__bf16)(x0 - (float)g0);
+                sm.bl[(r + 1) * RST + pe] = (__bf16)(x1 - (float)g1);
             }
         }
-        if (tid < kTile) wts[tid] = wr;
+        if (SEG && tid < kTile) sm.wts[tid] = wr;
         __syncthreads();
         if (t + 1 < tile1) load_tile(t + 1);
-        if (v0 >= p.nv) continue;        // wave without vectors (last group)
+        if (!active) continue;        // wave without vectors (last group)
 
         // ---- forward: Z[rt][ct] (rows: events 16 rt + 4q + e, column r16 of tile ct)
         f4 Z[2][CT];
@@ -161,8 +221,8 @@ __global__ __launch_bounds__(kThreads) void nll_batch_kernel(BatchArgs p) {
 #pragma unroll
             for (int rt = 0; rt < 2; ++rt) {
                 const int off = (16 * rt + r16) * RS16 + 32 * ks + 8 * q;
-                const h8 a_h = *reinterpret_cast<const h8 *>(&ah[off]);
-                const h8 a_l = *reinterpret_cast<const h8 *>(&al[off]);
+                const h8 a_h = *reinterpret_cast<const h8 *>(&sm.ah[off]);
+                const h8 a_l = *reinterpret_cast<const h8 *>(&sm.al[off]);
 #pragma unroll
                 for (int ct = 0; ct < CT; ++ct) {
                     Z[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_h, wh[ct][ks], Z[rt][ct], 0, 0, 0);
@@ -171,49 +231,20 @@ __global__ __launch_bounds__(kThreads) void nll_batch_kernel(BatchArgs p) {
                 }
             }
 
-        // ---- epilogue: per (event, vector) I, log2 I or w I, and U = z/I or w z,
-        // split into BF16 hi/lo in the adjoint's operand order
+        // ---- epilogue (the data segment's last tile masks absent events)
         b8 uh[CT], ul[CT];
-#pragma unroll
-        for (int g = 0; g < CT / 2; ++g) {
-            const bool vok = v0 + 16 * g + r16 < p.nv;
-            float ts = 0.f;
-#pragma unroll
-            for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int ev = 16 * rt + 4 * q + e;
-                    const bool ok = vok && t * kTile + ev < n;
-                    const float zr = Z[rt][2 * g][e], zi = Z[rt][2 * g + 1][e];
-                    const float I = fmaf(zr, zr, zi * zi);
-                    float ur, ui;
-                    if (seg == 0) {
-                        ts += ok ? __log2f(I) : 0.f;
-                        const float rI = ok ? __builtin_amdgcn_rcpf(I) : 0.f;
-                        ur = zr * rI;
-                        ui = zi * rI;
-                    } else {
-                        const float wv = ok ? wts[ev] : 0.f;
-                        ts = fmaf(wv, I, ts);
-                        ur = wv * zr;
-                        ui = wv * zi;
-                    }
-                    const int slot = 4 * rt + e;   // adjoint k order: events 4q+e, then 16+4q+e
-                    const __bf16 hr = (__bf16)ur, hi_ = (__bf16)ui;
-                    uh[2 * g][slot] = hr;
-                    uh[2 * g + 1][slot] = hi_;
-                    ul[2 * g][slot] = (__bf16)(ur - (float)hr);
-                    ul[2 * g + 1][slot] = (__bf16)(ui - (float)hi_);
-                }
-            tsum[g] += (double)ts;
-        }
+        const int64_t left = n - t * kTile;
+        if (SEG == 0 && left < kTile)
+            epilogue(Z, uh, ul, (int)left);
+        else
+            epilogue(Z, uh, ul, kTile);
 
         // ---- adjoint: D[ct][rt] += U^T (16 columns x 32 events) . A (32 events x 16 reals)
 #pragma unroll
         for (int rt = 0; rt < 2 * KS; ++rt) {
             const int rr = 16 * rt + r16;
-            const b8 b_h = *reinterpret_cast<const b8 *>(&bh[rr * RST + 8 * q]);
-            const b8 b_l = *reinterpret_cast<const b8 *>(&bl[rr * RST + 8 * q]);
+            const b8 b_h = *reinterpret_cast<const b8 *>(&sm.bh[rr * RST + 8 * q]);
+            const b8 b_l = *reinterpret_cast<const b8 *>(&sm.bl[rr * RST + 8 * q]);
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
                 D[ct][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uh[ct], b_h, D[ct][rt], 0, 0, 0);
@@ -222,7 +253,7 @@ __global__ __launch_bounds__(kThreads) void nll_batch_kernel(BatchArgs p) {
             }
         }
     }
-    if (v0 >= p.nv) return;
+    if (!active) return;
 
     // ---- per-vector scalar sums: lanes r16, r16 + 16, r16 + 32, r16 + 48 share a vector
 #pragma unroll
@@ -259,6 +290,15 @@ __global__ __launch_bounds__(kThreads) void nll_batch_kernel(BatchArgs p) {
                     dst[1] = (double)pi - (double)pr_o;      // Im G = P[ui, 2a] - P[ur, 2a+1]
                 }
             }
+}
+
+template <int KS, int CT>
+__global__ __launch_bounds__(kThreads) void nll_batch_kernel(BatchArgs p) {
+    __shared__ __attribute__((aligned(16))) BatchSmem<KS, CT> sm;
+    if ((int)blockIdx.x < p.nb[0])
+        batch_block<KS, CT, 0>(p, sm, (int)blockIdx.x);
+    else
+        batch_block<KS, CT, 1>(p, sm, (int)blockIdx.x - p.nb[0]);
 }
 
 // Per vector v (one block each): add the block partials of each segment in
