@@ -352,13 +352,17 @@ def extra_multifit(steps: int = 50):
     rows = sum(a.shape[0] + b.shape[0] for a, b, _, _ in samples)
     bytes_ = sum((a.shape[0] + b.shape[0]) * a.shape[1] * 8 for a, b, _, _ in samples)
     log(f"multifit: 64 fits, {rows} rows, {bytes_ / 1e9:.1f} GB, generated in {time.perf_counter() - t0:.0f}s")
+    t0 = time.perf_counter()
     mf = MultiFit(samples, V0)
     del samples
+    log(f"multifit: staged on the device in {time.perf_counter() - t0:.1f}s")
     cfgm, tune_ms = mf.autotune(reps=3)
+    log(f"multifit: autotuned {cfgm}: {tune_ms:.3f} ms per evaluation of all fits")
     mf.reset(V0)
     mf.step(2)
     mf.reset(V0)
     ms = mf.step(steps)
+    log(f"multifit: {ms:.3f} ms per minimiser iteration")
     _, f, st, it = mf.get()
     mf.close()
     return {"workload": "64 fits, N_D log-uniform in [1e4, 1e6], K uniform in 4..48, N_MC = 5 N_D, FP32",

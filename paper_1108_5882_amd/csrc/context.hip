@@ -420,6 +420,43 @@ pwa_status batch_mfma(pwa_ctx *ctx, int32_t nv, const double *V, double *nll, do
 
 }  // namespace
 
+namespace pwa {
+
+hipError_t stage_rows(void *dst, size_t dst_pitch, const void *src, size_t src_pitch, size_t width, size_t n,
+                      hipMemcpyKind kind, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    char *d = static_cast<char *>(dst);
+    const char *sp = static_cast<const char *>(src);
+    hipError_t e;
+    if (src_pitch == width && dst_pitch == width) {
+        e = hipMemcpyAsync(d, sp, width * n, kind, stream);
+        return e != hipSuccess ? e : hipStreamSynchronize(stream);
+    }
+    if (kind != hipMemcpyHostToDevice) {
+        if (dst_pitch > width && (e = hipMemsetAsync(d, 0, dst_pitch * n, stream)) != hipSuccess) return e;
+        e = hipMemcpy2DAsync(d, dst_pitch, sp, src_pitch, width, n, kind, stream);
+        return e != hipSuccess ? e : hipStreamSynchronize(stream);
+    }
+    const size_t rows_per_chunk = std::max<size_t>(1, (size_t)(64u << 20) / dst_pitch);
+    std::vector<char> buf;
+    try {
+        buf.assign(std::min(n, rows_per_chunk) * dst_pitch, 0);
+    } catch (...) {
+        return hipErrorOutOfMemory;
+    }
+    for (size_t r0 = 0; r0 < n; r0 += rows_per_chunk) {
+        const size_t nr = std::min(rows_per_chunk, n - r0);
+        for (size_t r = 0; r < nr; ++r) std::memcpy(buf.data() + r * dst_pitch, sp + (r0 + r) * src_pitch, width);
+        if ((e = hipMemcpyAsync(d + r0 * dst_pitch, buf.data(), nr * dst_pitch, hipMemcpyHostToDevice, stream)) !=
+                hipSuccess ||
+            (e = hipStreamSynchronize(stream)) != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace pwa
+
 extern "C" {
 
 pwa_status pwa_batch_fit(pwa_ctx *ctx, int32_t nv, const double *V0, int32_t iters, double *V,
@@ -596,13 +633,10 @@ pwa_status pwa_set_amplitudes(pwa_ctx *ctx, pwa_set which, const void *A, int64_
     const size_t row_bytes = 2 * eb * (size_t)ctx->ld;
     if (n > 0) {
         PWA_HIP(ctx, hipMalloc(&s.A, row_bytes * (size_t)n), "hipMalloc(amplitudes)");
-        if (ctx->ld > k)
-            PWA_HIP(ctx, hipMemsetAsync(s.A, 0, row_bytes * (size_t)n, ctx->stream),
-                    "hipMemsetAsync(amplitudes)");
         const hipMemcpyKind kind = where == PWA_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
-        PWA_HIP(ctx, hipMemcpy2DAsync(s.A, row_bytes, A, 2 * eb * (size_t)ld, 2 * eb * (size_t)k,
-                                      (size_t)n, kind, ctx->stream),
-                "hipMemcpy2DAsync(amplitudes)");
+        PWA_HIP(ctx, stage_rows(s.A, row_bytes, A, 2 * eb * (size_t)ld, 2 * eb * (size_t)k, (size_t)n, kind,
+                                ctx->stream),
+                "staging amplitudes");
         if (w) {
             PWA_HIP(ctx, hipMalloc(&s.w, eb * (size_t)n), "hipMalloc(weights)");
             PWA_HIP(ctx, hipMemcpyAsync(s.w, w, eb * (size_t)n, kind, ctx->stream),

@@ -168,6 +168,15 @@ hipError_t launch_lbfgs(const MultiFit *fits, int k_all, const double *out, int6
                         LbfgsState *states, int nfits, int m, double c1, double ftol,
                         hipStream_t stream);
 
+// Copies n rows of `width` bytes from src (rows src_pitch apart; host or
+// device memory per kind) to dst (rows dst_pitch apart, the bytes past width
+// zeroed).  Contiguous copies go in one transfer; host rows that need
+// re-striding are packed on the host in chunks first (a pitched copy from
+// pageable host memory moves row by row).  Returns when the rows are on the
+// device.
+hipError_t stage_rows(void *dst, size_t dst_pitch, const void *src, size_t src_pitch, size_t width, size_t n,
+                      hipMemcpyKind kind, hipStream_t stream);
+
 // Gram matrix of the MC rows (Eq. 3 bracket), FP64 result on the device.
 //   partials: device scratch of at least gram_partial_doubles(k, blocks) doubles.
 hipError_t launch_gram(pwa_prec prec, const void *A, const void *w, int64_t n, int64_t ld, int k,

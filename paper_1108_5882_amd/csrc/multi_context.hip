@@ -233,9 +233,8 @@ pwa_status pwa_multi_create(pwa_multi **out, int device, int32_t nfits, const pw
             }
             m->rows.push_back(buf);
             const void *src = seg ? (const void *)d.A_mc : (const void *)d.A_data;
-            if ((ft.ld > d.k && (e = hipMemset(buf, 0, row * n)) != hipSuccess) ||
-                (e = hipMemcpy2D(buf, row, src, 8 * (size_t)d.ld, 8 * (size_t)d.k, n, hipMemcpyHostToDevice)) !=
-                    hipSuccess) {
+            if ((e = stage_rows(buf, row, src, 8 * (size_t)d.ld, 8 * (size_t)d.k, n, hipMemcpyHostToDevice,
+                                m->stream)) != hipSuccess) {
                 mfail(m, PWA_E_HIP, "staging rows: %s", hipGetErrorString(e));
                 return bail(PWA_E_HIP);
             }
