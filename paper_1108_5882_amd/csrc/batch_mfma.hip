@@ -19,7 +19,8 @@
 // adjoint uses two-term BF16 splits of U and of the amplitudes (BF16 keeps
 // FP32's range, so the unbounded z/I needs no scale): 3 products.  MFMA
 // accumulation is FP32 within a block; each block covers at most
-// kTilesPerBlock tiles of one sample and writes FP64 partials per vector,
+// kTilesPerBlock tiles of one sample (spread evenly over whole rounds of
+// compute units) and writes FP64 partials per vector,
 // which a second kernel adds in block order (FP64) before forming NLL and
 // gradient per vector.
 #include "internal.hpp"
@@ -44,7 +45,7 @@ __device__ __forceinline__ int dpp_xor1(int x) {
 }
 __device__ __forceinline__ float xor1_f(float x) { return __int_as_float(dpp_xor1(__float_as_int(x))); }
 
-// Block b covers tiles [t0, t0 + kTilesPerBlock) of one segment (SEG: 0 data,
+// Block b covers tiles [b tpb, (b + 1) tpb) of one segment (SEG: 0 data,
 // 1 MC) for the vectors of blockIdx.y; each wave takes VPW = 8 CT vectors
 // (2 CT real columns in CT column tiles: re and im of 16 vectors per tile
 // pair).  Lanes of vectors past nv compute on zero weights and are never
@@ -63,8 +64,14 @@ struct BatchSmem {
     float wts[kTile];
 };
 
+// Two LDS buffers (one barrier per tile: the next tile is staged into the
+// other buffer after the current one is computed) when they fit in 64 KB.
+template <int KS, int CT>
+constexpr int batch_buffers() { return 2 * sizeof(BatchSmem<KS, CT>) <= 64 * 1024 ? 2 : 1; }
+
 template <int KS, int CT, int SEG>
-__device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT> &sm, int bseg) {
+__device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT> *bufs, int bseg) {
+    constexpr int NB = batch_buffers<KS, CT>();
     constexpr int kVPerWave = 8 * CT;
     constexpr int K2 = BatchSmem<KS, CT>::K2;
     constexpr int RS16 = BatchSmem<KS, CT>::RS16;
@@ -77,9 +84,9 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
     const int64_t n = p.n[SEG];
     const float *A = p.A[SEG];
     const float *w = SEG ? p.w : nullptr;
-    const int64_t tile0 = (int64_t)bseg * kTilesPerBlock;
+    const int64_t tile0 = (int64_t)bseg * p.tpb;
     const int64_t ntiles = (n + kTile - 1) / kTile;
-    const int64_t tile1 = tile0 + kTilesPerBlock < ntiles ? tile0 + kTilesPerBlock : ntiles;
+    const int64_t tile1 = tile0 + p.tpb < ntiles ? tile0 + p.tpb : ntiles;
     const int vg = (int)blockIdx.y * kWaves + wave;          // this wave's vector group
     const int v0 = vg * kVPerWave;
     const bool active = v0 < p.nv;                           // wave-uniform
@@ -132,7 +139,7 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
     // epilogue of one tile: per (event, vector) I, log2 I (data) or w I (MC),
     // and U = z / I (data) or w z (MC), split into BF16 hi/lo in the adjoint's
     // operand order (slot 4 rt + e holds event 16 rt + 4 q + e)
-    auto epilogue = [&](const f4 (&Z)[2][CT], b8 (&uh)[CT], b8 (&ul)[CT], int nvalid) {
+    auto epilogue = [&](const BatchSmem<KS, CT> &sm, const f4 (&Z)[2][CT], b8 (&uh)[CT], b8 (&ul)[CT], int nvalid) {
         float wv[8];
         if (SEG) {
             const f4 w0 = *reinterpret_cast<const f4 *>(&sm.wts[4 * q]);
@@ -178,13 +185,11 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
         }
     };
 
-    if (tile0 < tile1) load_tile(tile0);
-    for (int64_t t = tile0; t < tile1; ++t) {
-        // ---- stage the tile: FP16 (scaled) row-major planes and BF16 transposed
-        // planes; in the transposed planes event e sits at position
-        // 8 ((e mod 16) / 4) + (e mod 4) + 4 (e / 16), the adjoint's operand order,
-        // so that a lane reads its 8 values in one 16-byte access
-        __syncthreads();
+    // stage a tile from the registers into buffer b: FP16 (scaled) row-major
+    // planes and BF16 transposed planes; in the transposed planes event e sits
+    // at position 8 ((e mod 16) / 4) + (e mod 4) + 4 (e / 16), the adjoint's
+    // operand order, so that a lane reads its 8 values in one 16-byte access
+    auto stage = [&](BatchSmem<KS, CT> &b) {
 #pragma unroll
         for (int i = 0; i < kPer; ++i) {
             const int c = tid + i * kThreads;
@@ -193,23 +198,23 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
                 const float x0 = xr[i][0], x1 = xr[i][1];
                 const float y0 = x0 * p.ascale[r], y1 = x1 * p.ascale[r + 1];
                 const _Float16 h0 = (_Float16)y0, h1 = (_Float16)y1;
-                sm.ah[e * RS16 + r] = h0;
-                sm.ah[e * RS16 + r + 1] = h1;
-                sm.al[e * RS16 + r] = (_Float16)(y0 - (float)h0);
-                sm.al[e * RS16 + r + 1] = (_Float16)(y1 - (float)h1);
+                b.ah[e * RS16 + r] = h0;
+                b.ah[e * RS16 + r + 1] = h1;
+                b.al[e * RS16 + r] = (_Float16)(y0 - (float)h0);
+                b.al[e * RS16 + r + 1] = (_Float16)(y1 - (float)h1);
                 const int pe = 8 * ((e & 15) >> 2) + (e & 3) + 4 * (e >> 4);
                 const __bf16 g0 = (__bf16)x0, g1 = (__bf16)x1;
-                sm.bh[r * RST + pe] = g0;
-                sm.bh[(r + 1) * RST + pe] = g1;
-                sm.bl[r * RST + pe] = (__bf16)(x0 - (float)g0);
-                sm.bl[(r + 1) * RST + pe] = (__bf16)(x1 - (float)g1);
+                b.bh[r * RST + pe] = g0;
+                b.bh[(r + 1) * RST + pe] = g1;
+                b.bl[r * RST + pe] = (__bf16)(x0 - (float)g0);
+                b.bl[(r + 1) * RST + pe] = (__bf16)(x1 - (float)g1);
             }
         }
-        if (SEG && tid < kTile) sm.wts[tid] = wr;
-        __syncthreads();
-        if (t + 1 < tile1) load_tile(t + 1);
-        if (!active) continue;        // wave without vectors (last group)
+        if (SEG && tid < kTile) b.wts[tid] = wr;
+    };
 
+    // forward, epilogue and adjoint of the tile in buffer sm
+    auto compute = [&](const BatchSmem<KS, CT> &sm, int64_t t) {
         // ---- forward: Z[rt][ct] (rows: events 16 rt + 4q + e, column r16 of tile ct)
         f4 Z[2][CT];
 #pragma unroll
@@ -235,9 +240,9 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
         b8 uh[CT], ul[CT];
         const int64_t left = n - t * kTile;
         if (SEG == 0 && left < kTile)
-            epilogue(Z, uh, ul, (int)left);
+            epilogue(sm, Z, uh, ul, (int)left);
         else
-            epilogue(Z, uh, ul, kTile);
+            epilogue(sm, Z, uh, ul, kTile);
 
         // ---- adjoint: D[ct][rt] += U^T (16 columns x 32 events) . A (32 events x 16 reals)
 #pragma unroll
@@ -251,6 +256,34 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
                 D[ct][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uh[ct], b_l, D[ct][rt], 0, 0, 0);
                 D[ct][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ul[ct], b_h, D[ct][rt], 0, 0, 0);
             }
+        }
+    };
+
+    if (tile0 < tile1) load_tile(tile0);
+    if (NB == 2) {
+        // stage the first tile, then per tile: compute it, stage the next one
+        // into the other buffer, load the one after into registers, one barrier
+        if (tile0 < tile1) {
+            stage(bufs[0]);
+            if (tile0 + 1 < tile1) load_tile(tile0 + 1);
+        }
+        __syncthreads();
+        for (int64_t t = tile0; t < tile1; ++t) {
+            const int cur = (int)((t - tile0) & 1);
+            if (active) compute(bufs[cur], t);
+            if (t + 1 < tile1) {
+                stage(bufs[cur ^ 1]);
+                if (t + 2 < tile1) load_tile(t + 2);
+            }
+            __syncthreads();
+        }
+    } else {
+        for (int64_t t = tile0; t < tile1; ++t) {
+            __syncthreads();
+            stage(bufs[0]);
+            __syncthreads();
+            if (t + 1 < tile1) load_tile(t + 1);
+            if (active) compute(bufs[0], t);
         }
     }
     if (!active) return;
@@ -294,11 +327,11 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
 
 template <int KS, int CT>
 __global__ __launch_bounds__(kThreads) void nll_batch_kernel(BatchArgs p) {
-    __shared__ __attribute__((aligned(16))) BatchSmem<KS, CT> sm;
+    __shared__ __attribute__((aligned(16))) BatchSmem<KS, CT> bufs[batch_buffers<KS, CT>()];
     if ((int)blockIdx.x < p.nb[0])
-        batch_block<KS, CT, 0>(p, sm, (int)blockIdx.x);
+        batch_block<KS, CT, 0>(p, bufs, (int)blockIdx.x);
     else
-        batch_block<KS, CT, 1>(p, sm, (int)blockIdx.x - p.nb[0]);
+        batch_block<KS, CT, 1>(p, bufs, (int)blockIdx.x - p.nb[0]);
 }
 
 // Per vector v (one block each): add the block partials of each segment in
@@ -480,14 +513,22 @@ hipError_t launch_batch_weights(const BatchArgs &args, hipStream_t stream) {
     return hipGetLastError();
 }
 
-size_t batch_partial_doubles(int64_t n0, int64_t n1, int nv, int k) {
-    const int64_t nb = batch_blocks(n0) + batch_blocks(n1);
+size_t batch_partial_doubles(int64_t n0, int64_t n1, int tpb, int nv, int k) {
+    const int64_t nb = batch_blocks(n0, tpb) + batch_blocks(n1, tpb);
     return (size_t)nb * (size_t)nv * (size_t)(1 + 2 * k);
 }
 
-int64_t batch_blocks(int64_t n) {
+int batch_tiles_per_block(int64_t n0, int64_t n1, int cu) {
+    const int64_t tiles = (n0 + kTile - 1) / kTile + (n1 + kTile - 1) / kTile;
+    if (tiles == 0 || cu < 1) return kTilesPerBlock;
+    const int64_t rounds = (tiles + (int64_t)cu * kTilesPerBlock - 1) / ((int64_t)cu * kTilesPerBlock);
+    const int64_t tpb = (tiles + rounds * cu - 1) / (rounds * cu);
+    return (int)(tpb < 1 ? 1 : tpb);
+}
+
+int64_t batch_blocks(int64_t n, int tpb) {
     const int64_t tiles = (n + kTile - 1) / kTile;
-    return (tiles + kTilesPerBlock - 1) / kTilesPerBlock;
+    return (tiles + tpb - 1) / tpb;
 }
 
 int batch_ks(int k) { return (2 * k + 31) / 32; }

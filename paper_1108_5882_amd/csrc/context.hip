@@ -341,8 +341,9 @@ pwa_status batch_setup(pwa_ctx *ctx, int32_t nv, BatchArgs &a, int *gpad) {
     a.ld = ctx->ld;
     a.k = k;
     a.nv = nv;
-    a.nb[0] = (int32_t)batch_blocks(a.n[0]);
-    a.nb[1] = (int32_t)batch_blocks(a.n[1]);
+    a.tpb = batch_tiles_per_block(a.n[0], a.n[1], ctx->cu_count);
+    a.nb[0] = (int32_t)batch_blocks(a.n[0], a.tpb);
+    a.nb[1] = (int32_t)batch_blocks(a.n[1], a.tpb);
     a.pstride = 1 + 2 * k;
     a.extended = ctx->extended;
     a.n_gen = ctx->s[1].n_gen > 0 ? ctx->s[1].n_gen : 1.0;
@@ -356,7 +357,7 @@ pwa_status batch_setup(pwa_ctx *ctx, int32_t nv, BatchArgs &a, int *gpad) {
         (st = grow(ctx, &ctx->b_ascale, &ctx->b_cap[1], sizeof(float) * k2, "hipMalloc(scales)")) ||
         (st = grow(ctx, &ctx->b_vscale, &ctx->b_cap[2], sizeof(double) * nv, "hipMalloc(scales)")) ||
         (st = grow(ctx, &ctx->b_partials, &ctx->b_cap[4],
-                   sizeof(double) * std::max<size_t>(1, batch_partial_doubles(a.n[0], a.n[1], nv, k)),
+                   sizeof(double) * std::max<size_t>(1, batch_partial_doubles(a.n[0], a.n[1], a.tpb, nv, k)),
                    "hipMalloc(partials)")))
         return st;
     PWA_HIP(ctx, hipMemcpyAsync(ctx->b_ascale, ctx->ascale.data(), sizeof(float) * k2, hipMemcpyHostToDevice,

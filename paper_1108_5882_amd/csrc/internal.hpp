@@ -81,7 +81,8 @@ struct BatchArgs {
     int64_t ld;
     int32_t k;
     int32_t nv;                // number of production vectors
-    int32_t nb[2];             // blocks per segment (kTilesPerBlock tiles each)
+    int32_t nb[2];             // blocks per segment (tpb tiles each)
+    int32_t tpb;               // tiles (32 rows) per block
     int32_t pstride;           // doubles per (vector, block) partial: 1 + 2k
     int32_t extended;
     const void *wfrag;         // FP16 forward weights in MFMA fragment order
@@ -97,15 +98,19 @@ struct BatchArgs {
     double *out;               // [nv][ostride]: nll, grad[2k], flags
 };
 
-constexpr int kTilesPerBlock = 128;
+constexpr int kTilesPerBlock = 128;  // most tiles a block of the batched pass takes
 constexpr int kBatchWaves = 8;       // waves (vector groups) per block of the batched kernel
 
-int64_t batch_blocks(int64_t n);
+// Tiles per block for samples of n0 and n1 rows on cu compute units: the
+// fewest rounds of cu blocks with at most kTilesPerBlock tiles each, the
+// tiles spread evenly over them.
+int batch_tiles_per_block(int64_t n0, int64_t n1, int cu);
+int64_t batch_blocks(int64_t n, int tpb);
 int batch_ks(int k);
 int batch_ct(int k);                 // column tiles per wave (4 for k <= 32, else 2)
 int batch_vectors_per_wave(int k);   // 8 * batch_ct(k)
 int batch_vector_groups(int nv, int k);
-size_t batch_partial_doubles(int64_t n0, int64_t n1, int nv, int k);
+size_t batch_partial_doubles(int64_t n0, int64_t n1, int tpb, int nv, int k);
 hipError_t launch_amax(const float *A, int64_t n, int64_t ld, int k, unsigned *out,
                        hipStream_t stream);
 // The matrix-core pass (block partials per vector), then the per-vector combine.
