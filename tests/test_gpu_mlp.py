@@ -121,6 +121,28 @@ def test_predict_in_chunks_and_ragged(pwa, torch):
     assert np.array_equal(y, y2)              # a row's result does not depend on its batch
 
 
+def test_predict_at_screening_size(pwa, torch):
+    """10^5 candidates through 8192-row passes (the screening configuration), sampled rows
+    against the oracle, and the top 256 against the oracle's selection on the kernel's scores."""
+    n_in, hidden = 32, 256
+    P = synth.mlp_init(n_in, hidden, seed=4)
+    V = synth.eval_vectors(4, 100000, 16, stream=9)
+    Vi = np.empty((V.shape[0], 32))
+    Vi[:, 0::2], Vi[:, 1::2] = V.real, V.imag
+    with pwa.Mlp(n_in, hidden, max_batch=8192) as m:
+        m.set_params(P)
+        X = m.features(torch.from_numpy(Vi).cuda())
+        y = m.predict(X)
+        idx = m.select(y, 256).cpu().numpy()
+        y = y.cpu().numpy()
+    rows = np.random.default_rng(5).choice(100000, 3000, replace=False)
+    Xo = OM.features(V[rows]).astype(np.float32)
+    a = OM.forward(P, Xo, n_in, hidden, rounding=True)
+    sy, _ = _scales(P.astype(np.float64), Xo.astype(np.float64), np.zeros(3000), n_in, hidden)
+    _check("y (screening)", y[rows] - a["y"], sy)
+    assert np.array_equal(idx, OM.topk(y, 256))
+
+
 def test_adam_steps_match_oracle(pwa, torch):
     """Two training steps (same batch) against the oracle's Adam from the kernel's own gradients."""
     n_in, hidden, B = 32, 256, 512

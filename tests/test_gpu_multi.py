@@ -127,3 +127,27 @@ def test_multi_uneven_family_reduced():
         e_n, e_g = errors(reference(Ad, Am, Vg[f]), nll1[f], g1[f])
         assert e_n < 1e-6 and e_g < 1e-6, (f, e_n, e_g)
     mf.close()
+
+
+def test_multi_full_family_sampled():
+    """The 64-fit family at full size (5.4e7 rows), in the launch configuration the
+    benchmark times (autotuned); four fits checked against the oracle at 1e-6."""
+    from paper_1108_5882_amd import MultiFit
+    table = synth.multifit_table(64)
+    samples, V0 = [], []
+    for f, (nd, k, nm) in enumerate(table):
+        s = synth.make_sample(3, n_data=nd, n_mc=nm, k=k, fit=f)
+        samples.append((s.A_data, s.A_mc, None, None))
+        V0.append(synth.eval_vectors(3, 1, k, stream=f)[0])
+    _say("case multi full family")
+    mf = MultiFit(samples, V0)
+    cfg, ms = mf.autotune(reps=2)
+    nll, grads = mf.eval(V0)
+    mf.close()
+    _say(f"  autotuned {cfg}: {ms:.3f} ms per evaluation")
+    big = int(np.argmax([a.shape[0] for a, _, _, _ in samples]))
+    for f in sorted({0, 17, 63, big}):
+        Ad, Am, _, _ = samples[f]
+        e_n, e_g = errors(reference(Ad, Am, V0[f]), nll[f], grads[f])
+        _say(f"  fit {f} (N_D {Ad.shape[0]}, K {Ad.shape[1]}): e_nll {e_n:.2e} e_grad {e_g:.2e}")
+        assert e_n < 1e-6 and e_g < 1e-6, f
