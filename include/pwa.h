@@ -265,7 +265,7 @@ pwa_status pwa_multi_step(pwa_multi *m, int32_t steps, double *avg_ms);
 pwa_status pwa_multi_get(pwa_multi *m, double *V, double *nll, int32_t *status, int32_t *iters);
 
 /* Autotuner of the persistent launch: times the evaluation of all fits for
- * work items of 64 KB .. 1 MB of rows and 1 .. 8 blocks per compute unit,
+ * work items of 64 KB .. 4 MB of rows and 1 .. 16 blocks per compute unit,
  * `reps` launches each, keeps the fastest (and rebuilds the graph). */
 pwa_status pwa_multi_autotune(pwa_multi *m, int32_t reps, int64_t *item_bytes, int32_t *blocks_per_cu,
                               double *best_ms);

@@ -370,8 +370,8 @@ pwa_status pwa_multi_autotune(pwa_multi *m, int32_t reps, int64_t *item_bytes, i
     if (!m) return mfail(nullptr, PWA_E_INVAL, "null argument");
     if (reps < 1) reps = 1;
     DevGuard dg(m->device);
-    static const int64_t kBytes[] = {64 << 10, 128 << 10, 256 << 10, 512 << 10, 1 << 20};
-    static const int kBpc[] = {1, 2, 3, 4, 6, 8};
+    static const int64_t kBytes[] = {64 << 10, 128 << 10, 256 << 10, 512 << 10, 1 << 20, 2 << 20, 4 << 20};
+    static const int kBpc[] = {1, 2, 3, 4, 6, 8, 12, 16};
     hipEvent_t e0, e1;
     M_HIP(m, hipEventCreate(&e0), "hipEventCreate");
     M_HIP(m, hipEventCreate(&e1), "hipEventCreate");
