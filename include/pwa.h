@@ -140,10 +140,18 @@ pwa_status pwa_nll_grad_async(pwa_ctx *ctx, const double *V_dev, double *out_dev
  *               of-two scale per vector); the adjoint sums conj(A) u use
  *               two-term BF16 splits of u and of the amplitudes; FP32
  *               accumulation within a block of at most 4096 events, FP64 across
- *               blocks.  FP32 contexts only.
+ *               blocks; the first-order effect of rounding V to the split
+ *               weights is added from the adjoint sums.  A data event whose
+ *               coherent sum is small against |V| |A_i| gets a large relative
+ *               error in z / I; the gradient error is stated, not bounded.
+ *            3  as 2, but data events with |z| < |V| |A_i| / 32 are left out
+ *               of the matrix-core sums, flagged, and their terms recomputed
+ *               exactly in FP64 by a second kernel: NLL and gradient of every
+ *               vector as accurate as the single-V path.
+ *            Splits 2 and 3 need an FP32 context.
  * V may hold any number of vectors; the FP64 results land in host memory.
  * Errors as pwa_nll (PWA_E_DOMAIN if some vector's NLL is +inf; every output
- * is written); PWA_E_UNSUPPORTED for another split, or split 2 in an FP64
+ * is written); PWA_E_UNSUPPORTED for another split, or split 2 or 3 in an FP64
  * context. */
 pwa_status pwa_nll_batch(pwa_ctx *ctx, int32_t nv, const double *V, double *nll,
                          double *grad, int32_t split);

@@ -277,7 +277,8 @@ class Context:
 
     def nll_batch(self, Vs, grad: bool = True, split: int = 2):
         """NLL (and gradients) for the rows of Vs [nv, k] complex (or [nv, 2k] real).
-        split 2: matrix-core pass for all vectors; split 0: one streaming pass each."""
+        split 2: matrix-core pass for all vectors; split 3: the same with small
+        coherent sums recomputed exactly; split 0: one streaming pass each."""
         Vs = np.asarray(Vs)
         if np.iscomplexobj(Vs):
             v = np.empty((Vs.shape[0], 2 * Vs.shape[1]))

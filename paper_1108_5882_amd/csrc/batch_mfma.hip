@@ -69,7 +69,11 @@ struct BatchSmem {
 template <int KS, int CT>
 constexpr int batch_buffers() { return 2 * sizeof(BatchSmem<KS, CT>) <= 64 * 1024 ? 2 : 1; }
 
-template <int KS, int CT, int SEG>
+// REF (data segment only): events whose coherent sum is small against the
+// bound |z| <= |V| |A_i| (|Z'|^2 < c^2 t_v^2 |V|^2 |A_i|^2, c^2 = p.cthr2) are
+// left out of the sums and marked in p.flags, one 64-bit lane mask per
+// (tile, vector group, group g, rt, e); batch_refine_kernel adds them exactly.
+template <int KS, int CT, int SEG, bool REF>
 __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT> *bufs, int bseg) {
     constexpr int NB = batch_buffers<KS, CT>();
     constexpr int kVPerWave = 8 * CT;
@@ -90,6 +94,24 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
     const int vg = (int)blockIdx.y * kWaves + wave;          // this wave's vector group
     const int v0 = vg * kVPerWave;
     const bool active = v0 < p.nv;                           // wave-uniform
+    constexpr bool kRef = REF && SEG == 0;
+    // flag thresholds of this lane's vectors: c^2 t_v^2 |V|^2 (-1 for vectors past nv),
+    // and 1 / t_v^2 (a power of two): the log is taken of the unscaled I = I' / t_v^2,
+    // whose magnitude keeps the FP32 log and the FP32 tile sums accurate
+    float thr[CT / 2], inv_t2[CT / 2];
+#pragma unroll
+    for (int g = 0; g < CT / 2; ++g) {
+        thr[g] = -1.f;
+        inv_t2[g] = 1.f;
+        const int v = v0 + 16 * g + r16;
+        if (SEG == 0 && v < p.nv) inv_t2[g] = (float)(1.0 / (p.vscale[v] * p.vscale[v]));
+        if (kRef && v < p.nv) {
+            const double *Vv = p.V + (int64_t)v * p.vstride;
+            double n2 = 0.0;
+            for (int a = 0; a < 2 * p.k; ++a) n2 += Vv[a] * Vv[a];
+            thr[g] = (float)((double)p.cthr2 * p.vscale[v] * p.vscale[v] * n2);
+        }
+    }
 
     // forward weights of this wave's vectors, fragment order [hi/lo][ct][ks][lane]
     h8 wh[CT][KS], wl[CT][KS];
@@ -130,18 +152,19 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
                 if (row < n && r < nreal) xr[i] = *reinterpret_cast<const f2 *>(A + 2 * (row * p.ld) + r);
             }
         }
-        if (SEG && tid < kTile) {
+        if ((SEG || kRef) && tid < kTile) {
             const int64_t row = t * kTile + tid;
-            wr = row < n ? (w ? w[row] : 1.f) : 0.f;
+            wr = row < n ? (SEG ? (w ? w[row] : 1.f) : p.rnorm[row]) : 0.f;
         }
     };
 
     // epilogue of one tile: per (event, vector) I, log2 I (data) or w I (MC),
     // and U = z / I (data) or w z (MC), split into BF16 hi/lo in the adjoint's
     // operand order (slot 4 rt + e holds event 16 rt + 4 q + e)
-    auto epilogue = [&](const BatchSmem<KS, CT> &sm, const f4 (&Z)[2][CT], b8 (&uh)[CT], b8 (&ul)[CT], int nvalid) {
-        float wv[8];
-        if (SEG) {
+    auto epilogue = [&](const BatchSmem<KS, CT> &sm, const f4 (&Z)[2][CT], b8 (&uh)[CT], b8 (&ul)[CT], int nvalid,
+                        int64_t t) {
+        float wv[8];                // MC weights, or the rows' |A|^2 when flagging
+        if (SEG || kRef) {
             const f4 w0 = *reinterpret_cast<const f4 *>(&sm.wts[4 * q]);
             const f4 w1 = *reinterpret_cast<const f4 *>(&sm.wts[16 + 4 * q]);
 #pragma unroll
@@ -162,10 +185,17 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
                     const float I = fmaf(zr, zr, zi * zi);
                     float ur, ui;
                     if (SEG == 0) {
-                        if (nvalid < kTile && 16 * rt + 4 * q + e >= nvalid) {
+                        const bool absent = nvalid < kTile && 16 * rt + 4 * q + e >= nvalid;
+                        const bool flag = kRef && !absent && I < thr[g] * wv[slot];
+                        if (kRef) {
+                            const unsigned long long mask = __ballot(flag);
+                            if (lane == 0)
+                                p.flags[((t * p.ngroups_pad + vg) * (CT / 2) + g) * 8 + slot] = mask;
+                        }
+                        if (absent || flag) {
                             ur = ui = 0.f;
                         } else {
-                            ts += __log2f(I);
+                            ts += __log2f(I * inv_t2[g]);
                             const float rI = __builtin_amdgcn_rcpf(I);
                             ur = zr * rI;
                             ui = zi * rI;
@@ -210,7 +240,7 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
                 b.bl[(r + 1) * RST + pe] = (__bf16)(x1 - (float)g1);
             }
         }
-        if (SEG && tid < kTile) b.wts[tid] = wr;
+        if ((SEG || kRef) && tid < kTile) b.wts[tid] = wr;
     };
 
     // forward, epilogue and adjoint of the tile in buffer sm
@@ -240,9 +270,9 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
         b8 uh[CT], ul[CT];
         const int64_t left = n - t * kTile;
         if (SEG == 0 && left < kTile)
-            epilogue(sm, Z, uh, ul, (int)left);
+            epilogue(sm, Z, uh, ul, (int)left, t);
         else
-            epilogue(sm, Z, uh, ul, kTile);
+            epilogue(sm, Z, uh, ul, kTile, t);
 
         // ---- adjoint: D[ct][rt] += U^T (16 columns x 32 events) . A (32 events x 16 reals)
 #pragma unroll
@@ -325,18 +355,107 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
             }
 }
 
-template <int KS, int CT>
+template <int KS, int CT, bool REF>
 __global__ __launch_bounds__(kThreads) void nll_batch_kernel(BatchArgs p) {
     __shared__ __attribute__((aligned(16))) BatchSmem<KS, CT> bufs[batch_buffers<KS, CT>()];
     if ((int)blockIdx.x < p.nb[0])
-        batch_block<KS, CT, 0>(p, bufs, (int)blockIdx.x);
+        batch_block<KS, CT, 0, REF>(p, bufs, (int)blockIdx.x);
     else
-        batch_block<KS, CT, 1>(p, bufs, (int)blockIdx.x - p.nb[0]);
+        batch_block<KS, CT, 1, REF>(p, bufs, (int)blockIdx.x - p.nb[0]);
+}
+
+// Exact terms of the flagged data events: block (b, y) and its wave w take the
+// flag words of data block b's tiles for vector group 8 y + w, in tile, word and
+// bit order, and add each flagged event's terms, in the units of the block
+// partials (log2 I, conj(A) z / (I t_v)), to the partial of its
+// vector and block: every partial is updated by one wave, in a fixed order.
+// z is formed in FP64 from the FP32 amplitudes (one wave per event, lanes over
+// waves a), like the single-V path.
+template <int CT>
+__global__ __launch_bounds__(kThreads) void batch_refine_kernel(BatchArgs p) {
+    constexpr int kVPerWave = 8 * CT;
+    constexpr int kWords = 8 * (CT / 2);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int vg = (int)blockIdx.y * kWaves + wave;
+    const int v0 = vg * kVPerWave;
+    if (v0 >= p.nv) return;
+    const int64_t n = p.n[0];
+    const int64_t ntiles = (n + kTile - 1) / kTile;
+    const int64_t tile0 = (int64_t)blockIdx.x * p.tpb;
+    const int64_t tile1 = tile0 + p.tpb < ntiles ? tile0 + p.tpb : ntiles;
+    const int nblk = p.nb[0] + p.nb[1];
+    const int k = p.k;
+    for (int64_t t = tile0; t < tile1; ++t) {
+        const unsigned long long *fw = p.flags + (t * p.ngroups_pad + vg) * kWords;
+        for (int wi = 0; wi < kWords; ++wi) {
+            unsigned long long m = fw[wi];
+            const int g = wi / 8, rt = (wi % 8) / 4, e = wi % 4;
+            while (m) {
+                const int l = __builtin_ctzll(m);
+                m &= m - 1;
+                const int ev = 16 * rt + 4 * (l >> 4) + e;
+                const int v = v0 + 16 * g + (l & 15);
+                const int64_t row = t * kTile + ev;
+                const double *V = p.V + (int64_t)v * p.vstride;
+                double ar = 0.0, ai = 0.0, zr = 0.0, zi = 0.0;
+                if (lane < k) {
+                    ar = (double)p.A[0][2 * (row * p.ld + lane)];
+                    ai = (double)p.A[0][2 * (row * p.ld + lane) + 1];
+                    zr = V[2 * lane] * ar - V[2 * lane + 1] * ai;
+                    zi = V[2 * lane] * ai + V[2 * lane + 1] * ar;
+                }
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    zr += __shfl_xor(zr, off);
+                    zi += __shfl_xor(zi, off);
+                }
+                const double I = zr * zr + zi * zi;
+                const double tv = p.vscale[v];
+                double *dst = p.partials + ((int64_t)v * nblk + blockIdx.x) * p.pstride;
+                if (lane == 0) dst[0] += log2(I);
+                if (lane < k) {
+                    const double ur = zr / (I * tv), ui = zi / (I * tv);
+                    dst[1 + 2 * lane] += ar * ur + ai * ui;        // Re conj(A_a) u
+                    dst[2 + 2 * lane] += ar * ui - ai * ur;        // Im conj(A_a) u
+                }
+            }
+        }
+    }
+}
+
+// |A_i|^2 of each row (FP64 sum of the FP32 values, stored as FP32).
+__global__ void rownorm_kernel(const float *A, int64_t n, int64_t ld, int k, float *out) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        const float *x = A + 2 * r * ld;
+        double s = 0.0;
+        for (int a = 0; a < 2 * k; ++a) s += (double)x[a] * (double)x[a];
+        out[r] = (float)s;
+    }
+}
+
+// The FP16 hi + lo pair the forward weights carry for a weight x (scaled by
+// t / s); the combine evaluates the same expression to know the weights the
+// matrix cores used.
+struct WeightSplit {
+    _Float16 hi, lo;
+};
+__device__ __forceinline__ WeightSplit split_weight(double x) {
+    const _Float16 hi = (_Float16)(float)x;
+    return WeightSplit{hi, (_Float16)(float)(x - (double)(float)hi)};
 }
 
 // Per vector v (one block each): add the block partials of each segment in
 // block order, undo the per-vector scale t_v of the forward weights, and form
 // NLL and gradient (Eq. 2 or Eq. 3 form; streamed MC or the MC matrix).
+//
+// The matrix cores summed with the weights V~ the FP16 hi + lo pairs hold,
+// not V; the difference dV = V - V~ (about 2^-22 |V|) is the same for every
+// event, so it does not average out over the sums.  Its first-order effect is
+// added here from the adjoint sums the pass produced:
+//   sum_i ln I_i(V) = sum_i ln I_i(V~) + 2 Re sum_a dV_a conj(G_a),
+//   sum_j w_j I_j(V) = sum_j w_j I_j(V~) + 2 Re sum_a dV_a conj(H_a),
+// with G_a = sum_i conj(A_ia) z_i / I_i and H_a = sum_j w_j conj(A_ja) z_j
+// (the second-order terms are about 2^-44 of the sums).
 // The block partials of a segment are summed by G = 256 / pstride thread
 // groups (group g takes blocks g, g + G, ...; threads of a group take the
 // pstride values of a block, so each block's partial row is read contiguously),
@@ -345,6 +464,7 @@ __global__ __launch_bounds__(256) void nll_batch_combine_kernel(BatchArgs p) {
     __shared__ double tot[2][1 + 2 * PWA_MAX_K];
     __shared__ double grp[256];
     __shared__ double mv[2 * PWA_MAX_K];
+    __shared__ double dv[2 * PWA_MAX_K];
     __shared__ double s_c;
     const int v = blockIdx.x, tid = threadIdx.x;
     const int pst = p.pstride;
@@ -370,6 +490,11 @@ __global__ __launch_bounds__(256) void nll_batch_combine_kernel(BatchArgs p) {
     }
     const double tv = p.vscale[v];
     const double *V = p.V + (int64_t)v * p.vstride;
+    for (int i = tid; i < 2 * k; i += 256) {
+        const double sr = (double)p.ascale[i];
+        const WeightSplit ws = split_weight(V[i] * tv / sr);
+        dv[i] = V[i] - ((double)ws.hi + (double)ws.lo) * sr / tv;
+    }
     if (p.gram) {
         for (int a = tid; a < k; a += 256) {
             double r = 0.0, i = 0.0;
@@ -386,8 +511,15 @@ __global__ __launch_bounds__(256) void nll_batch_combine_kernel(BatchArgs p) {
     double *out = p.out + (int64_t)v * p.ostride;
     if (tid == 0) {
         const double nd = p.nd_total;
-        // Z = t_v z, so sum ln I = ln 2 sum log2 I' - 2 N_D ln t_v and sum w I = sum w I' / t_v^2
-        const double sum_log = tot[0][0] * 0.69314718055994530942 - 2.0 * nd * log(tv);
+        // Z' = t_v z: the data sums hold log2 I (unscaled) and conj(A) u / t_v; sum w I = sum w I' / t_v^2
+        // first-order terms of the weight rounding (data: G = t_v x data sums;
+        // MC: H = MC sums / t_v); the data's log sum is of the unscaled I
+        double dlog = 0.0, ds = 0.0;
+        for (int i = 0; i < 2 * k; ++i) {
+            dlog += dv[i] * tot[0][1 + i] * tv;
+            ds += dv[i] * tot[1][1 + i] / tv;
+        }
+        const double sum_log = tot[0][0] * 0.69314718055994530942 + 2.0 * dlog;
         double S, c;
         if (p.gram) {
             double s = 0.0;
@@ -395,7 +527,7 @@ __global__ __launch_bounds__(256) void nll_batch_combine_kernel(BatchArgs p) {
             S = s;
             c = p.extended ? 1.0 : nd / S;
         } else {
-            const double s_raw = tot[1][0] / (tv * tv);
+            const double s_raw = tot[1][0] / (tv * tv) + 2.0 * ds;
             S = s_raw / p.n_gen;
             c = p.extended ? 1.0 / p.n_gen : nd / s_raw;
         }
@@ -485,8 +617,8 @@ __global__ void batch_wfrag_kernel(BatchArgs p, int ngroups_pad) {
             const double wv = (ct & 1) == 0 ? ((r & 1) == 0 ? vr : -vi) : ((r & 1) == 0 ? vi : vr);
             x = wv * p.vscale[v] / (double)p.ascale[r];
         }
-        const _Float16 hi = (_Float16)(float)x;
-        const _Float16 lo = (_Float16)(float)(x - (double)(float)hi);
+        const WeightSplit ws = split_weight(x);
+        const _Float16 hi = ws.hi, lo = ws.lo;
         const size_t base = ((((size_t)grp * 2 + 0) * CT + ct) * KS + kk) * 64 + lane;
         const size_t basel = ((((size_t)grp * 2 + 1) * CT + ct) * KS + kk) * 64 + lane;
         wf[base * 8 + e] = hi;
@@ -551,21 +683,53 @@ hipError_t launch_amax(const float *A, int64_t n, int64_t ld, int k, unsigned *o
     return hipGetLastError();
 }
 
-hipError_t launch_batch(const BatchArgs &args, hipStream_t stream) {
+hipError_t launch_batch(const BatchArgs &args, bool refine, hipStream_t stream) {
     const int nblk = args.nb[0] + args.nb[1];
     if (nblk > 0) {
         const int gy = (batch_vector_groups(args.nv, args.k) + kWaves - 1) / kWaves;
         const dim3 grid(nblk, gy);
+#define PWA_BATCH_LAUNCH(KS_, CT_)                                                                   \
+    do {                                                                                             \
+        if (refine)                                                                                  \
+            hipLaunchKernelGGL((nll_batch_kernel<KS_, CT_, true>), grid, dim3(kThreads), 0, stream, args);  \
+        else                                                                                         \
+            hipLaunchKernelGGL((nll_batch_kernel<KS_, CT_, false>), grid, dim3(kThreads), 0, stream, args); \
+    } while (0)
         switch (batch_ks(args.k)) {
-            case 1: hipLaunchKernelGGL((nll_batch_kernel<1, 4>), grid, dim3(kThreads), 0, stream, args); break;
-            case 2: hipLaunchKernelGGL((nll_batch_kernel<2, 4>), grid, dim3(kThreads), 0, stream, args); break;
-            case 3: hipLaunchKernelGGL((nll_batch_kernel<3, 2>), grid, dim3(kThreads), 0, stream, args); break;
-            case 4: hipLaunchKernelGGL((nll_batch_kernel<4, 2>), grid, dim3(kThreads), 0, stream, args); break;
+            case 1: PWA_BATCH_LAUNCH(1, 4); break;
+            case 2: PWA_BATCH_LAUNCH(2, 4); break;
+            case 3: PWA_BATCH_LAUNCH(3, 2); break;
+            case 4: PWA_BATCH_LAUNCH(4, 2); break;
             default: return hipErrorInvalidValue;
         }
+#undef PWA_BATCH_LAUNCH
         return hipGetLastError();
     }
     return hipSuccess;
+}
+
+hipError_t launch_batch_refine(const BatchArgs &args, hipStream_t stream) {
+    if (args.nb[0] == 0) return hipSuccess;
+    const int gy = (batch_vector_groups(args.nv, args.k) + kWaves - 1) / kWaves;
+    const dim3 grid(args.nb[0], gy);
+    if (batch_ct(args.k) == 4)
+        hipLaunchKernelGGL((batch_refine_kernel<4>), grid, dim3(kThreads), 0, stream, args);
+    else
+        hipLaunchKernelGGL((batch_refine_kernel<2>), grid, dim3(kThreads), 0, stream, args);
+    return hipGetLastError();
+}
+
+size_t batch_flag_words(int64_t n0, int nv, int k) {
+    const int64_t tiles = (n0 + kTile - 1) / kTile;
+    const int gpad = (batch_vector_groups(nv, k) + kWaves - 1) / kWaves * kWaves;
+    return (size_t)tiles * gpad * 8 * (batch_ct(k) / 2);
+}
+
+hipError_t launch_rownorm(const float *A, int64_t n, int64_t ld, int k, float *out, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(rownorm_kernel, dim3(blocks), dim3(256), 0, stream, A, n, ld, k, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_batch_combine(const BatchArgs &args, hipStream_t stream) {

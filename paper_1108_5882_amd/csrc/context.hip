@@ -80,6 +80,11 @@ struct pwa_ctx {
     void *b_partials = nullptr, *b_out = nullptr;
     size_t b_cap[6] = {0, 0, 0, 0, 0, 0};
     unsigned *b_amax = nullptr;
+    // exact refinement of small coherent sums: |A_i|^2 of the data rows, flag words
+    bool rnorm_valid = false;
+    float *b_rnorm = nullptr;
+    void *b_flags = nullptr;
+    size_t flags_cap = 0;
 
     std::string err;
 };
@@ -362,6 +367,8 @@ pwa_status batch_setup(pwa_ctx *ctx, int32_t nv, BatchArgs &a, int *gpad) {
         return st;
     PWA_HIP(ctx, hipMemcpyAsync(ctx->b_ascale, ctx->ascale.data(), sizeof(float) * k2, hipMemcpyHostToDevice,
                                 ctx->stream), "hipMemcpyAsync(scales)");
+    a.ngroups_pad = *gpad;
+    a.cthr2 = kRefineC2;
     a.wfrag = ctx->b_wfrag;
     a.ascale = static_cast<const float *>(ctx->b_ascale);
     a.vscale = static_cast<const double *>(ctx->b_vscale);
@@ -370,8 +377,9 @@ pwa_status batch_setup(pwa_ctx *ctx, int32_t nv, BatchArgs &a, int *gpad) {
 }
 
 // Batched NLL (and gradient) of nv host vectors on the matrix cores: device
-// weights from V, the matrix-core pass, the per-vector combine.
-pwa_status batch_mfma(pwa_ctx *ctx, int32_t nv, const double *V, double *nll, double *grad) {
+// weights from V, the matrix-core pass (with refine: flags for data events with
+// small coherent sums, then their exact terms), the per-vector combine.
+pwa_status batch_mfma(pwa_ctx *ctx, int32_t nv, const double *V, double *nll, double *grad, bool refine) {
     DeviceGuard dg(ctx->device);
     const int k = ctx->k;
     BatchArgs a;
@@ -388,6 +396,22 @@ pwa_status batch_mfma(pwa_ctx *ctx, int32_t nv, const double *V, double *nll, do
     a.vstride = 2 * k;
     a.out = static_cast<double *>(ctx->b_out);
     a.ostride = 2 * k + 2;
+    if (refine && a.n[0] > 0) {
+        if (!ctx->rnorm_valid) {
+            if (ctx->b_rnorm) (void)hipFree(ctx->b_rnorm);
+            ctx->b_rnorm = nullptr;
+            PWA_HIP(ctx, hipMalloc(&ctx->b_rnorm, sizeof(float) * (size_t)a.n[0]), "hipMalloc(row norms)");
+            PWA_HIP(ctx, launch_rownorm(a.A[0], a.n[0], a.ld, k, ctx->b_rnorm, ctx->stream), "row norm launch");
+            ctx->rnorm_valid = true;
+        }
+        if ((st = grow(ctx, &ctx->b_flags, &ctx->flags_cap,
+                       sizeof(unsigned long long) * batch_flag_words(a.n[0], nv, k), "hipMalloc(flags)")))
+            return st;
+        a.rnorm = ctx->b_rnorm;
+        a.flags = static_cast<unsigned long long *>(ctx->b_flags);
+    } else {
+        refine = false;
+    }
     hipError_t e = launch_batch_weights(a, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "batched weights launch");
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -396,8 +420,10 @@ pwa_status batch_mfma(pwa_ctx *ctx, int32_t nv, const double *V, double *nll, do
         PWA_HIP(ctx, hipEventCreate(&e1), "hipEventCreate");
         PWA_HIP(ctx, hipEventRecord(e0, ctx->stream), "hipEventRecord");
     }
-    e = launch_batch(a, ctx->stream);
+    e = launch_batch(a, refine, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "batched kernel launch");
+    if (refine && (e = launch_batch_refine(a, ctx->stream)) != hipSuccess)
+        return hip_fail(ctx, e, "refinement launch");
     if (ctx->timing) {
         PWA_HIP(ctx, hipEventRecord(e1, ctx->stream), "hipEventRecord");
         ctx->batch_events.emplace_back(e0, e1);
@@ -496,7 +522,7 @@ pwa_status pwa_batch_fit(pwa_ctx *ctx, int32_t nv, const double *V0, int32_t ite
     if (e == hipSuccess) e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         hipError_t ec = launch_batch_weights(a, ctx->stream);
-        if (ec == hipSuccess) ec = launch_batch(a, ctx->stream);
+        if (ec == hipSuccess) ec = launch_batch(a, false, ctx->stream);
         if (ec == hipSuccess) ec = launch_batch_combine(a, ctx->stream);
         if (ec == hipSuccess) ec = launch_lbfgs(nullptr, k, d_out, ostride, d_states, nv, 8, 1e-4, 1e-12, ctx->stream);
         e = hipStreamEndCapture(ctx->stream, &graph);
@@ -593,7 +619,7 @@ pwa_status pwa_destroy(pwa_ctx *ctx) {
         }
     if (ctx->gram) (void)hipFree(ctx->gram);
     for (void *b : {ctx->b_wfrag, ctx->b_ascale, ctx->b_vscale, ctx->b_V, ctx->b_partials, ctx->b_out,
-                    (void *)ctx->b_amax})
+                    (void *)ctx->b_amax, (void *)ctx->b_rnorm, ctx->b_flags})
         if (b) (void)hipFree(b);
     if (ctx->partials) (void)hipFree(ctx->partials);
     if (ctx->out_dev) (void)hipFree(ctx->out_dev);
@@ -629,6 +655,7 @@ pwa_status pwa_set_amplitudes(pwa_ctx *ctx, pwa_set which, const void *A, int64_
     free_sample(s);
     if (which == PWA_MC) ctx->gram_valid = false;
     ctx->amax_valid = false;
+    if (which == PWA_DATA) ctx->rnorm_valid = false;
 
     const size_t eb = elem_bytes(ctx->prec);
     const size_t row_bytes = 2 * eb * (size_t)ctx->ld;
@@ -701,8 +728,9 @@ pwa_status pwa_nll_batch(pwa_ctx *ctx, int32_t nv, const double *V, double *nll,
                          int32_t split) {
     if (!ctx) return fail(nullptr, PWA_E_INVAL, "null context");
     if (nv < 0 || (nv > 0 && (!V || !nll))) return fail(ctx, PWA_E_INVAL, "bad batch arguments");
-    if (split != 0 && split != 2) return fail(ctx, PWA_E_UNSUPPORTED, "split %d not available", split);
-    if (split == 2 && ctx->prec != PWA_F32)
+    if (split != 0 && split != 2 && split != 3)
+        return fail(ctx, PWA_E_UNSUPPORTED, "split %d not available", split);
+    if (split >= 2 && ctx->prec != PWA_F32)
         return fail(ctx, PWA_E_UNSUPPORTED, "the matrix-core path needs an FP32 context");
     for (int64_t i = 0; i < (int64_t)nv * 2 * ctx->k; ++i)
         if (!std::isfinite(V[i])) return fail(ctx, PWA_E_INVAL, "V is not finite");
@@ -721,7 +749,7 @@ pwa_status pwa_nll_batch(pwa_ctx *ctx, int32_t nv, const double *V, double *nll,
         }
         return domain ? fail(ctx, PWA_E_DOMAIN, "non-positive intensity or normalisation") : PWA_OK;
     }
-    return batch_mfma(ctx, nv, V, nll, grad);
+    return batch_mfma(ctx, nv, V, nll, grad, split == 3);
 }
 
 pwa_status pwa_last_flags(pwa_ctx *ctx, uint32_t *flags) {

@@ -96,6 +96,11 @@ struct BatchArgs {
     double nd_total;
     double *partials;          // [nv][blocks][pstride]
     double *out;               // [nv][ostride]: nll, grad[2k], flags
+    // exact refinement of small coherent sums (data segment; pwa_nll_batch split 3)
+    const float *rnorm;        // |A_i|^2 per data row
+    unsigned long long *flags; // batch_flag_words() lane masks
+    float cthr2;               // c^2 of the flag test |z| < c |V| |A_i|
+    int32_t ngroups_pad;       // vector groups rounded up to whole blocks
 };
 
 constexpr int kTilesPerBlock = 128;  // most tiles a block of the batched pass takes
@@ -114,7 +119,13 @@ size_t batch_partial_doubles(int64_t n0, int64_t n1, int tpb, int nv, int k);
 hipError_t launch_amax(const float *A, int64_t n, int64_t ld, int k, unsigned *out,
                        hipStream_t stream);
 // The matrix-core pass (block partials per vector), then the per-vector combine.
-hipError_t launch_batch(const BatchArgs &args, hipStream_t stream);
+// With refine, data events with small coherent sums are flagged instead of
+// summed, and launch_batch_refine adds them exactly (before the combine).
+hipError_t launch_batch(const BatchArgs &args, bool refine, hipStream_t stream);
+hipError_t launch_batch_refine(const BatchArgs &args, hipStream_t stream);
+size_t batch_flag_words(int64_t n0, int nv, int k);
+hipError_t launch_rownorm(const float *A, int64_t n, int64_t ld, int k, float *out, hipStream_t stream);
+constexpr float kRefineC2 = 1.0f / 1024.0f;   // c = 1/32
 hipError_t launch_batch_combine(const BatchArgs &args, hipStream_t stream);
 // Device-side forward weights from args.V: the per-vector scales, then the
 // FP16 fragments (args.wfrag, sized for the padded vector groups).
