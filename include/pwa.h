@@ -144,10 +144,11 @@ pwa_status pwa_nll_grad_async(pwa_ctx *ctx, const double *V_dev, double *out_dev
  *               weights is added from the adjoint sums.  A data event whose
  *               coherent sum is small against |V| |A_i| gets a large relative
  *               error in z / I; the gradient error is stated, not bounded.
- *            3  as 2, but data events with |z| < |V| |A_i| / 32 are left out
+ *            3  as 2, but data events with |z| < c |V| |A_i| are left out
  *               of the matrix-core sums, flagged, and their terms recomputed
- *               exactly in FP64 by a second kernel: NLL and gradient of every
- *               vector as accurate as the single-V path.
+ *               exactly in FP64 by a second kernel (c^2 = min(1/1024, 4/N_D):
+ *               the gradient scale grows with N_D, one event's error does
+ *               not): NLL and gradient of every vector within 1e-6.
  *            Splits 2 and 3 need an FP32 context.
  * V may hold any number of vectors; the FP64 results land in host memory.
  * Errors as pwa_nll (PWA_E_DOMAIN if some vector's NLL is +inf; every output

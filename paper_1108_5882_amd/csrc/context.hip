@@ -368,7 +368,10 @@ pwa_status batch_setup(pwa_ctx *ctx, int32_t nv, BatchArgs &a, int *gpad) {
     PWA_HIP(ctx, hipMemcpyAsync(ctx->b_ascale, ctx->ascale.data(), sizeof(float) * k2, hipMemcpyHostToDevice,
                                 ctx->stream), "hipMemcpyAsync(scales)");
     a.ngroups_pad = *gpad;
-    a.cthr2 = kRefineC2;
+    // c^2 of the flag test: 1/1024, lowered to 4 / N_D for larger samples (the
+    // gradient scale grows with N_D while one event's error does not, so the
+    // expected number of events in the flagged region stays constant)
+    a.cthr2 = (float)std::min<double>(kRefineC2, 4.0 / std::max<double>(1.0, (double)nd));
     a.wfrag = ctx->b_wfrag;
     a.ascale = static_cast<const float *>(ctx->b_ascale);
     a.vscale = static_cast<const double *>(ctx->b_vscale);

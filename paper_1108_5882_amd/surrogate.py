@@ -5,7 +5,7 @@ Fits are repeated from many starting points because a minimiser can stop in a
 local minimum (Berger, Section 2); with many parameters, repeating fits from
 random starting values becomes very expensive (Section 4).  The pipeline:
 
-  1. pairs    exact NLL of training vectors (matrix-core batched pass);
+  1. pairs    NLL of training vectors (matrix-core batched pass, split 3);
   2. train    the network on (canonical features, ln(1 + NLL - min NLL));
   3. screen   predict every candidate start and keep the `top` best;
   4. refine   batched L-BFGS from the kept starts (pwa_batch_fit);
@@ -33,14 +33,15 @@ def _interleave(V: np.ndarray) -> np.ndarray:
 
 
 def exact_pairs(ctx, V: np.ndarray, chunk: int = 2048) -> np.ndarray:
-    """NLL of every row of V [n, k] by the matrix-core pass, `chunk` vectors per call
-    (a domain failure gives +inf for that vector only)."""
+    """NLL of every row of V [n, k] by the matrix-core pass with small coherent sums
+    recomputed exactly (split 3), `chunk` vectors per call (a domain failure gives
+    +inf for that vector only)."""
     from ._lib import DomainError
     out = np.empty(V.shape[0])
     for c in range(0, V.shape[0], chunk):
         part = V[c:c + chunk]
         try:
-            out[c:c + part.shape[0]] = ctx.nll_batch(part, grad=False, split=2)
+            out[c:c + part.shape[0]] = ctx.nll_batch(part, grad=False, split=3)
         except DomainError:
             out[c:c + part.shape[0]] = [_one(ctx, v) for v in part]
     return out
@@ -49,7 +50,7 @@ def exact_pairs(ctx, V: np.ndarray, chunk: int = 2048) -> np.ndarray:
 def _one(ctx, v):
     from ._lib import DomainError
     try:
-        return ctx.nll_batch(v[None], grad=False, split=2)[0]
+        return ctx.nll_batch(v[None], grad=False, split=3)[0]
     except DomainError:
         return np.inf
 

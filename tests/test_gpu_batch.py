@@ -12,9 +12,9 @@ vector; gradient median below 1e-6, 95th percentile below 1e-4, maximum below
 vectors meet 1e-6.
 
 Split 3 is split 2 plus an exact treatment of those events: a data event
-whose coherent sum is small against the bound |z| <= |V| |A_i| (|z| < |V| |A_i|
-/ 32) is left out of the matrix-core sums, flagged, and recomputed in FP64 by a
-second kernel; it meets 1e-6 for every vector.  Split 0 (one exact streaming
+whose coherent sum is small against the bound |z| <= |V| |A_i| (|z| < c |V|
+|A_i|, c^2 = min(1/1024, 4/N_D)) is left out of the matrix-core sums, flagged,
+and recomputed in FP64 by a second kernel; it meets 1e-6 for every vector.  Split 0 (one exact streaming
 pass per vector) meets 1e-6 everywhere and is tested here too.
 """
 import sys
