@@ -72,7 +72,9 @@ constexpr int batch_buffers() { return 2 * sizeof(BatchSmem<KS, CT>) <= 64 * 102
 // REF (data segment only): events whose coherent sum is small against the
 // bound |z| <= |V| |A_i| (|Z'|^2 < c^2 t_v^2 |V|^2 |A_i|^2, c^2 = p.cthr2) are
 // left out of the sums and marked in p.flags, one 64-bit lane mask per
-// (tile, vector group, group g, rt, e); batch_refine_kernel adds them exactly.
+// (vector group, tile, group g, rt, e), in that order of significance, so the
+// words of one vector group over consecutive tiles are contiguous;
+// batch_refine_kernel adds them exactly.
 template <int KS, int CT, int SEG, bool REF>
 __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT> *bufs, int bseg) {
     constexpr int NB = batch_buffers<KS, CT>();
@@ -173,6 +175,7 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
                 wv[4 + e] = w1[e];
             }
         }
+        unsigned long long fword = 0ull;    // lane 8 g + slot: the flag mask of (g, slot)
 #pragma unroll
         for (int g = 0; g < CT / 2; ++g) {
             float ts = 0.f;
@@ -189,8 +192,7 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
                         const bool flag = kRef && !absent && I < thr[g] * wv[slot];
                         if (kRef) {
                             const unsigned long long mask = __ballot(flag);
-                            if (lane == 0)
-                                p.flags[((t * p.ngroups_pad + vg) * (CT / 2) + g) * 8 + slot] = mask;
+                            if (lane == 8 * g + slot) fword = mask;
                         }
                         if (absent || flag) {
                             ur = ui = 0.f;
@@ -213,6 +215,7 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
                 }
             tsum[g] += (double)ts;
         }
+        if (kRef && lane < 8 * (CT / 2)) p.flags[((int64_t)vg * ntiles + t) * (8 * (CT / 2)) + lane] = fword;
     };
 
     // stage a tile from the registers into buffer b: FP16 (scaled) row-major
@@ -375,6 +378,7 @@ template <int CT>
 __global__ __launch_bounds__(kThreads) void batch_refine_kernel(BatchArgs p) {
     constexpr int kVPerWave = 8 * CT;
     constexpr int kWords = 8 * (CT / 2);
+    constexpr int kLoads = 4;                       // flag words in flight per lane
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int vg = (int)blockIdx.y * kWaves + wave;
     const int v0 = vg * kVPerWave;
@@ -385,38 +389,56 @@ __global__ __launch_bounds__(kThreads) void batch_refine_kernel(BatchArgs p) {
     const int64_t tile1 = tile0 + p.tpb < ntiles ? tile0 + p.tpb : ntiles;
     const int nblk = p.nb[0] + p.nb[1];
     const int k = p.k;
-    for (int64_t t = tile0; t < tile1; ++t) {
-        const unsigned long long *fw = p.flags + (t * p.ngroups_pad + vg) * kWords;
-        for (int wi = 0; wi < kWords; ++wi) {
-            unsigned long long m = fw[wi];
-            const int g = wi / 8, rt = (wi % 8) / 4, e = wi % 4;
-            while (m) {
-                const int l = __builtin_ctzll(m);
-                m &= m - 1;
-                const int ev = 16 * rt + 4 * (l >> 4) + e;
-                const int v = v0 + 16 * g + (l & 15);
-                const int64_t row = t * kTile + ev;
-                const double *V = p.V + (int64_t)v * p.vstride;
-                double ar = 0.0, ai = 0.0, zr = 0.0, zi = 0.0;
-                if (lane < k) {
-                    ar = (double)p.A[0][2 * (row * p.ld + lane)];
-                    ai = (double)p.A[0][2 * (row * p.ld + lane) + 1];
-                    zr = V[2 * lane] * ar - V[2 * lane + 1] * ai;
-                    zi = V[2 * lane] * ai + V[2 * lane + 1] * ar;
-                }
+    // this wave's words for tiles [tile0, tile1) are contiguous: the lanes read
+    // 64 of them per load and the wave visits only the nonzero ones, in order
+    const int64_t nwords = (tile1 - tile0) * kWords;
+    const unsigned long long *fw = p.flags + ((int64_t)vg * ntiles + tile0) * kWords;
+    for (int64_t base = 0; base < nwords; base += 64 * kLoads) {
+        unsigned long long mw[kLoads];
 #pragma unroll
-                for (int off = 1; off < 64; off <<= 1) {
-                    zr += __shfl_xor(zr, off);
-                    zi += __shfl_xor(zi, off);
-                }
-                const double I = zr * zr + zi * zi;
-                const double tv = p.vscale[v];
-                double *dst = p.partials + ((int64_t)v * nblk + blockIdx.x) * p.pstride;
-                if (lane == 0) dst[0] += log2(I);
-                if (lane < k) {
-                    const double ur = zr / (I * tv), ui = zi / (I * tv);
-                    dst[1 + 2 * lane] += ar * ur + ai * ui;        // Re conj(A_a) u
-                    dst[2 + 2 * lane] += ar * ui - ai * ur;        // Im conj(A_a) u
+        for (int j = 0; j < kLoads; ++j) {
+            const int64_t i = base + 64 * j + lane;
+            mw[j] = i < nwords ? fw[i] : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < kLoads; ++j) {
+            unsigned long long nz = __ballot(mw[j] != 0ull);
+            while (nz) {
+                const int src = __builtin_ctzll(nz);
+                nz &= nz - 1;
+                unsigned long long m = __shfl(mw[j], src);
+                const int64_t i = base + 64 * j + src;
+                const int64_t t = tile0 + i / kWords;
+                const int wi = (int)(i % kWords);
+                const int g = wi / 8, rt = (wi % 8) / 4, e = wi % 4;
+                while (m) {
+                    const int l = __builtin_ctzll(m);
+                    m &= m - 1;
+                    const int ev = 16 * rt + 4 * (l >> 4) + e;
+                    const int v = v0 + 16 * g + (l & 15);
+                    const int64_t row = t * kTile + ev;
+                    const double *V = p.V + (int64_t)v * p.vstride;
+                    double ar = 0.0, ai = 0.0, zr = 0.0, zi = 0.0;
+                    if (lane < k) {
+                        ar = (double)p.A[0][2 * (row * p.ld + lane)];
+                        ai = (double)p.A[0][2 * (row * p.ld + lane) + 1];
+                        zr = V[2 * lane] * ar - V[2 * lane + 1] * ai;
+                        zi = V[2 * lane] * ai + V[2 * lane + 1] * ar;
+                    }
+#pragma unroll
+                    for (int off = 1; off < 64; off <<= 1) {
+                        zr += __shfl_xor(zr, off);
+                        zi += __shfl_xor(zi, off);
+                    }
+                    const double I = zr * zr + zi * zi;
+                    const double tv = p.vscale[v];
+                    double *dst = p.partials + ((int64_t)v * nblk + blockIdx.x) * p.pstride;
+                    if (lane == 0) dst[0] += log2(I);
+                    if (lane < k) {
+                        const double ur = zr / (I * tv), ui = zi / (I * tv);
+                        dst[1 + 2 * lane] += ar * ur + ai * ui;        // Re conj(A_a) u
+                        dst[2 + 2 * lane] += ar * ui - ai * ur;        // Im conj(A_a) u
+                    }
                 }
             }
         }
