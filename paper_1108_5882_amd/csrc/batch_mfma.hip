@@ -69,6 +69,9 @@ struct BatchSmem {
 template <int KS, int CT>
 constexpr int batch_buffers() { return 2 * sizeof(BatchSmem<KS, CT>) <= 64 * 1024 ? 2 : 1; }
 
+// v_writelane_b32: writes a wave-uniform value into one lane of a register
+__device__ unsigned writelane_u32(unsigned v, int lane, unsigned old) __asm("llvm.amdgcn.writelane.i32");
+
 // REF (data segment only): events whose coherent sum is small against the
 // bound |z| <= |V| |A_i| (|Z'|^2 < c^2 t_v^2 |V|^2 |A_i|^2, c^2 = p.cthr2) are
 // left out of the sums and marked in p.flags, one 64-bit lane mask per
@@ -175,10 +178,13 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
                 wv[4 + e] = w1[e];
             }
         }
-        unsigned long long fword = 0ull;    // lane 8 g + slot: the flag mask of (g, slot)
 #pragma unroll
         for (int g = 0; g < CT / 2; ++g) {
             float ts = 0.f;
+            // the flag masks of (g, slot): with one k-step (KS = 1) lane `slot` gathers
+            // them for one store per group; with more, registers are short (the
+            // gather costs spills) and lane 0 stores each mask
+            unsigned fw_lo = 0u, fw_hi = 0u;
 #pragma unroll
             for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
@@ -192,7 +198,12 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
                         const bool flag = kRef && !absent && I < thr[g] * wv[slot];
                         if (kRef) {
                             const unsigned long long mask = __ballot(flag);
-                            if (lane == 8 * g + slot) fword = mask;
+                            if constexpr (KS == 1) {
+                                fw_lo = writelane_u32((unsigned)mask, slot, fw_lo);
+                                fw_hi = writelane_u32((unsigned)(mask >> 32), slot, fw_hi);
+                            } else if (lane == 0) {
+                                p.flags[((int64_t)vg * ntiles + t) * (8 * (CT / 2)) + 8 * g + slot] = mask;
+                            }
                         }
                         if (absent || flag) {
                             ur = ui = 0.f;
@@ -214,8 +225,10 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
                     ul[2 * g + 1][slot] = (__bf16)(ui - (float)hi_);
                 }
             tsum[g] += (double)ts;
+            if (kRef && KS == 1 && lane < 8)
+                p.flags[((int64_t)vg * ntiles + t) * (8 * (CT / 2)) + 8 * g + lane] =
+                    ((unsigned long long)fw_hi << 32) | fw_lo;
         }
-        if (kRef && lane < 8 * (CT / 2)) p.flags[((int64_t)vg * ntiles + t) * (8 * (CT / 2)) + lane] = fword;
     };
 
     // stage a tile from the registers into buffer b: FP16 (scaled) row-major

@@ -130,20 +130,36 @@ __global__ __launch_bounds__(kMT) void multi_stream_kernel(MultiArgs p) {
     }
 }
 
-// One block per fit: adds the fit's item partials in item order and forms
-// NLL and gradient (Eq. 2 form), written to out[fit][2k + 2].
-__global__ __launch_bounds__(128) void multi_combine_kernel(MultiArgs p) {
-    __shared__ double tot[2][1 + 2 * PWA_MAX_K];
+// One block per fit: adds the fit's item partials and forms NLL and gradient
+// (Eq. 2 form), written to out[fit][2k + 2].  Slice s of a column adds items
+// i0 + s, i0 + s + kSlices, ... (independent loads, several in flight); the
+// slices are then added in slice order, so the result does not depend on
+// which block evaluated which item.
+constexpr int kCombineThreads = 1024;
+constexpr int kSlices = 16;
+
+__global__ __launch_bounds__(kCombineThreads) void multi_combine_kernel(MultiArgs p) {
+    __shared__ double part[kSlices][2][1 + 2 * kMultiMaxLd];
+    __shared__ double tot[2][1 + 2 * kMultiMaxLd];
     __shared__ double s_c;
     const int f = blockIdx.x, tid = threadIdx.x;
     const MultiFit fit = p.fits[f];
     const int k = fit.k, ps = 1 + 2 * (int)fit.ld;
-    for (int idx = tid; idx < 2 * ps; idx += 128) {
-        const int sg = idx / ps, cc = idx % ps;
+    for (int idx = tid; idx < kSlices * 2 * ps; idx += kCombineThreads) {
+        const int sl = idx / (2 * ps), rem = idx % (2 * ps);
+        const int sg = rem / ps, cc = rem % ps;
         const int i0 = sg ? fit.item_mc0 : fit.item_data0;
         const int i1 = sg ? fit.item_mc1 : fit.item_data1;
         double s = 0.0;
-        for (int i = i0; i < i1; ++i) s += p.partials[(int64_t)i * kMultiSlot + cc];
+#pragma unroll 4
+        for (int i = i0 + sl; i < i1; i += kSlices) s += p.partials[(int64_t)i * kMultiSlot + cc];
+        part[sl][sg][cc] = s;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < 2 * ps; idx += kCombineThreads) {
+        const int sg = idx / ps, cc = idx % ps;
+        double s = 0.0;
+        for (int sl = 0; sl < kSlices; ++sl) s += part[sl][sg][cc];
         tot[sg][cc] = s;
     }
     __syncthreads();
@@ -171,7 +187,7 @@ __global__ __launch_bounds__(128) void multi_combine_kernel(MultiArgs p) {
         s_c = c;
     }
     __syncthreads();
-    for (int i = tid; i < 2 * k; i += 128) out[1 + i] = 2.0 * (-tot[0][1 + i] + s_c * tot[1][1 + i]);
+    for (int i = tid; i < 2 * k; i += kCombineThreads) out[1 + i] = 2.0 * (-tot[0][1 + i] + s_c * tot[1][1 + i]);
     if (f == 0 && tid == 0) *p.item_counter = 0u;      // ready for the next launch
 }
 
@@ -181,7 +197,7 @@ hipError_t launch_multi_eval(const MultiArgs &args, int blocks, hipStream_t stre
     hipLaunchKernelGGL(multi_stream_kernel, dim3(blocks), dim3(kMT), 0, stream, args);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(multi_combine_kernel, dim3(args.n_fits), dim3(128), 0, stream, args);
+    hipLaunchKernelGGL(multi_combine_kernel, dim3(args.n_fits), dim3(kCombineThreads), 0, stream, args);
     return hipGetLastError();
 }
 
