@@ -28,6 +28,10 @@
 #include <algorithm>
 #include <cmath>
 
+// v_writelane_b32 (the LLVM intrinsic): writes a wave-uniform value into one lane
+// of a register, leaving the other lanes as they are
+__device__ unsigned writelane_u32(unsigned v, int lane, unsigned old) __asm("llvm.amdgcn.writelane.i32");
+
 namespace pwa {
 namespace {
 
@@ -68,9 +72,6 @@ struct BatchSmem {
 // other buffer after the current one is computed) when they fit in 64 KB.
 template <int KS, int CT>
 constexpr int batch_buffers() { return 2 * sizeof(BatchSmem<KS, CT>) <= 64 * 1024 ? 2 : 1; }
-
-// v_writelane_b32: writes a wave-uniform value into one lane of a register
-__device__ unsigned writelane_u32(unsigned v, int lane, unsigned old) __asm("llvm.amdgcn.writelane.i32");
 
 // REF (data segment only): events whose coherent sum is small against the
 // bound |z| <= |V| |A_i| (|Z'|^2 < c^2 t_v^2 |V|^2 |A_i|^2, c^2 = p.cthr2) are
@@ -166,20 +167,10 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
     // epilogue of one tile: per (event, vector) I, log2 I (data) or w I (MC),
     // and U = z / I (data) or w z (MC), split into BF16 hi/lo in the adjoint's
     // operand order (slot 4 rt + e holds event 16 rt + 4 q + e)
-    auto epilogue = [&](const BatchSmem<KS, CT> &sm, const f4 (&Z)[2][CT], b8 (&uh)[CT], b8 (&ul)[CT], int nvalid,
-                        int64_t t) {
-        float wv[8];                // MC weights, or the rows' |A|^2 when flagging
-        if (SEG || kRef) {
-            const f4 w0 = *reinterpret_cast<const f4 *>(&sm.wts[4 * q]);
-            const f4 w1 = *reinterpret_cast<const f4 *>(&sm.wts[16 + 4 * q]);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                wv[e] = w0[e];
-                wv[4 + e] = w1[e];
-            }
-        }
-#pragma unroll
-        for (int g = 0; g < CT / 2; ++g) {
+    // (column group g: column tiles 2g and 2g + 1, vectors 16 g + r16)
+    auto epilogue = [&](const float (&wv)[8], const f4 (&Z)[2][CT], b8 (&uh)[CT], b8 (&ul)[CT], int nvalid,
+                        int64_t t, const int g) {
+        {
             float ts = 0.f;
             // the flag masks of (g, slot): with one k-step (KS = 1) lane `slot` gathers
             // them for one store per group; with more, registers are short (the
@@ -260,13 +251,8 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
     };
 
     // forward, epilogue and adjoint of the tile in buffer sm
-    auto compute = [&](const BatchSmem<KS, CT> &sm, int64_t t) {
-        // ---- forward: Z[rt][ct] (rows: events 16 rt + 4q + e, column r16 of tile ct)
-        f4 Z[2][CT];
-#pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-            for (int ct = 0; ct < CT; ++ct) Z[rt][ct] = f4{0.f, 0.f, 0.f, 0.f};
+    // forward products of column group g only (used when the groups are interleaved)
+    auto forward_g = [&](const BatchSmem<KS, CT> &sm, f4 (&Z)[2][CT], const int g) {
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
@@ -275,34 +261,104 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
                 const h8 a_h = *reinterpret_cast<const h8 *>(&sm.ah[off]);
                 const h8 a_l = *reinterpret_cast<const h8 *>(&sm.al[off]);
 #pragma unroll
-                for (int ct = 0; ct < CT; ++ct) {
+                for (int ct = 2 * g; ct < 2 * g + 2; ++ct) {
                     Z[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_h, wh[ct][ks], Z[rt][ct], 0, 0, 0);
                     Z[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_h, wl[ct][ks], Z[rt][ct], 0, 0, 0);
                     Z[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_l, wh[ct][ks], Z[rt][ct], 0, 0, 0);
                 }
             }
-
-        // ---- epilogue (the data segment's last tile masks absent events)
-        b8 uh[CT], ul[CT];
-        const int64_t left = n - t * kTile;
-        if (SEG == 0 && left < kTile)
-            epilogue(sm, Z, uh, ul, (int)left, t);
-        else
-            epilogue(sm, Z, uh, ul, kTile, t);
-
-        // ---- adjoint: D[ct][rt] += U^T (16 columns x 32 events) . A (32 events x 16 reals)
+    };
+    // adjoint D[ct][rt] += U^T (16 columns x 32 events) . A (32 events x 16 reals) for the
+    // column tiles [c0, c1)
+    auto adjoint = [&](const BatchSmem<KS, CT> &sm, const b8 (&uh)[CT], const b8 (&ul)[CT], const int c0,
+                       const int c1) {
 #pragma unroll
         for (int rt = 0; rt < 2 * KS; ++rt) {
             const int rr = 16 * rt + r16;
             const b8 b_h = *reinterpret_cast<const b8 *>(&sm.bh[rr * RST + 8 * q]);
             const b8 b_l = *reinterpret_cast<const b8 *>(&sm.bl[rr * RST + 8 * q]);
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct) {
+            for (int ct = c0; ct < c1; ++ct) {
                 D[ct][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uh[ct], b_h, D[ct][rt], 0, 0, 0);
                 D[ct][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uh[ct], b_l, D[ct][rt], 0, 0, 0);
                 D[ct][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ul[ct], b_h, D[ct][rt], 0, 0, 0);
             }
         }
+    };
+
+    // one tile; nvalid < kTile only for the data segment's last tile
+    auto tile_body = [&](const BatchSmem<KS, CT> &sm, int64_t t, const int nvalid) __attribute__((always_inline)) {
+        f4 Z[2][CT];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) Z[rt][ct] = f4{0.f, 0.f, 0.f, 0.f};
+        b8 uh[CT], ul[CT];
+        float wv[8];                // MC weights, or the rows' |A|^2 when flagging
+        auto load_wv = [&]() __attribute__((always_inline)) {
+            if (SEG || kRef) {
+                const f4 w0 = *reinterpret_cast<const f4 *>(&sm.wts[4 * q]);
+                const f4 w1 = *reinterpret_cast<const f4 *>(&sm.wts[16 + 4 * q]);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    wv[e] = w0[e];
+                    wv[4 + e] = w1[e];
+                }
+            }
+        };
+
+        if constexpr (KS == 1 || CT < 4) {
+            // forward of all column tiles (one A fragment load each), epilogue, adjoint
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                for (int rt = 0; rt < 2; ++rt) {
+                    const int off = (16 * rt + r16) * RS16 + 32 * ks + 8 * q;
+                    const h8 a_h = *reinterpret_cast<const h8 *>(&sm.ah[off]);
+                    const h8 a_l = *reinterpret_cast<const h8 *>(&sm.al[off]);
+#pragma unroll
+                    for (int ct = 0; ct < CT; ++ct) {
+                        Z[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_h, wh[ct][ks], Z[rt][ct], 0, 0, 0);
+                        Z[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_h, wl[ct][ks], Z[rt][ct], 0, 0, 0);
+                        Z[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_l, wh[ct][ks], Z[rt][ct], 0, 0, 0);
+                    }
+                }
+            load_wv();
+            if (nvalid < kTile) {
+#pragma unroll
+                for (int g = 0; g < CT / 2; ++g) epilogue(wv, Z, uh, ul, nvalid, t, g);
+            } else {
+#pragma unroll
+                for (int g = 0; g < CT / 2; ++g) epilogue(wv, Z, uh, ul, kTile, t, g);
+            }
+            adjoint(sm, uh, ul, 0, CT);
+        } else {
+            // two column groups with two or more k-steps: the matrix products of one
+            // group are interleaved with the vector epilogue of the other (F0 | F1 with
+            // E0 | A0 with E1 | A1), one product per three vector instructions; the two
+            // waves sharing a SIMD otherwise run the same phase of a tile
+            constexpr int kM = 12 * KS;                 // products per group and direction
+            forward_g(sm, Z, 0);
+            forward_g(sm, Z, 1);
+            load_wv();
+            epilogue(wv, Z, uh, ul, nvalid, t, 0);
+            adjoint(sm, uh, ul, 0, 2);
+            epilogue(wv, Z, uh, ul, nvalid, t, 1);
+            adjoint(sm, uh, ul, 2, 4);
+#pragma unroll
+            for (int i = 0; i < kM; ++i) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+#pragma unroll
+            for (int i = 0; i < 2 * kM; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < kM; ++i) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        }
+    };
+    auto compute = [&](const BatchSmem<KS, CT> &sm, int64_t t) {
+        const int64_t left = n - t * kTile;
+        tile_body(sm, t, (SEG == 0 && left < kTile) ? (int)left : kTile);
     };
 
     if (tile0 < tile1) load_tile(tile0);
@@ -458,13 +514,28 @@ __global__ __launch_bounds__(kThreads) void batch_refine_kernel(BatchArgs p) {
     }
 }
 
-// |A_i|^2 of each row (FP64 sum of the FP32 values, stored as FP32).
+// |A_i|^2 of each row (FP64 sums of the FP32 values, stored as FP32): 8 lanes per
+// row, each reading 16-byte chunks (two complex values), summed over the 8 lanes.
+// Only the first k complex values count (a borrowed sample's padding is not read
+// as data).  Rows are 16-byte aligned (ld even).
 __global__ void rownorm_kernel(const float *A, int64_t n, int64_t ld, int k, float *out) {
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
-        const float *x = A + 2 * r * ld;
+    typedef float f4r __attribute__((ext_vector_type(4)));
+    const int sub = threadIdx.x & 7;
+    const int nch = (k + 1) / 2;
+    const int64_t groups = (int64_t)gridDim.x * blockDim.x / 8;
+    // the 8 lanes of a row share r, so they leave the loop together
+    for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 8; r < n; r += groups) {
+        const f4r *x = reinterpret_cast<const f4r *>(A + 2 * r * ld);
         double s = 0.0;
-        for (int a = 0; a < 2 * k; ++a) s += (double)x[a] * (double)x[a];
-        out[r] = (float)s;
+        for (int c = sub; c < nch; c += 8) {
+            const f4r v = x[c];
+            s += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+            if (2 * c + 1 < k) s += (double)v.z * (double)v.z + (double)v.w * (double)v.w;
+        }
+        s += __shfl_xor(s, 1);
+        s += __shfl_xor(s, 2);
+        s += __shfl_xor(s, 4);
+        if (sub == 0) out[r] = (float)s;
     }
 }
 
@@ -762,7 +833,7 @@ size_t batch_flag_words(int64_t n0, int nv, int k) {
 
 hipError_t launch_rownorm(const float *A, int64_t n, int64_t ld, int k, float *out, hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    const int blocks = (int)std::min<int64_t>((8 * n + 255) / 256, 16384);
     hipLaunchKernelGGL(rownorm_kernel, dim3(blocks), dim3(256), 0, stream, A, n, ld, k, out);
     return hipGetLastError();
 }
