@@ -157,6 +157,24 @@ pwa_status pwa_nll_grad_async(pwa_ctx *ctx, const double *V_dev, double *out_dev
 pwa_status pwa_nll_batch(pwa_ctx *ctx, int32_t nv, const double *V, double *nll,
                          double *grad, int32_t split);
 
+/* Device-side variant of pwa_nll_batch for graph capture and device
+ * minimisers (the same arithmetic, launch configuration and results).
+ *   V_dev    device pointer, nv x 2k doubles, read when the kernels run
+ *   out_dev  device pointer, nv x (2k + 2) doubles, written when the kernels
+ *            run: per vector [0] NLL (+inf on a domain failure), [1 .. 2k]
+ *            gradient, [2k + 1] status flags (0 = ok, nonzero = domain failure)
+ *   split    0, 2 or 3 as in pwa_nll_batch (0: nv single-V launches)
+ * Enqueues on the context's stream and returns: no wait, no allocation, no
+ * host copy.  Splits 2 and 3 use workspace and lazily built inputs (operand
+ * scales, the Gram matrix in PWA_MC_GRAM mode, row norms for split 3) that a
+ * synchronous pwa_nll_batch call with at least nv vectors and the same split
+ * on the current samples creates; without them the call returns PWA_E_STATE
+ * and enqueues nothing.  V_dev and out_dev must not overlap.
+ * Errors (detected on the host only): PWA_E_INVAL, PWA_E_STATE,
+ * PWA_E_UNSUPPORTED, PWA_E_HIP. */
+pwa_status pwa_nll_batch_async(pwa_ctx *ctx, int32_t nv, const double *V_dev, double *out_dev,
+                               int32_t split);
+
 /* Minimise the NLL from nv starting vectors at once on the context's samples
  * (multi-start, Section 2): every iteration evaluates all trial vectors with
  * the matrix-core pass of pwa_nll_batch (split 2) and advances one device

@@ -25,7 +25,8 @@ MAX_K = 64
 # every entry point declared in include/pwa.h
 EXPORTS = [
     "pwa_create", "pwa_destroy", "pwa_set_amplitudes", "pwa_set_mc_mode", "pwa_nll",
-    "pwa_nll_grad", "pwa_nll_grad_async", "pwa_nll_batch", "pwa_last_flags", "pwa_last_error",
+    "pwa_nll_grad", "pwa_nll_grad_async", "pwa_nll_batch", "pwa_nll_batch_async", "pwa_last_flags",
+    "pwa_last_error",
     "pwa_layout_ld", "pwa_set_timing", "pwa_kernel_time", "pwa_get_stream_cfg",
     "pwa_set_stream_cfg", "pwa_autotune", "pwa_batch_kernel_time",
     "pwa_multi_create", "pwa_multi_destroy", "pwa_multi_eval", "pwa_multi_reset", "pwa_multi_step",
@@ -105,6 +106,7 @@ def load(path: str = LIB_PATH):
         "pwa_nll_grad": [P, P, P, P],
         "pwa_nll_grad_async": [P, P, P],
         "pwa_nll_batch": [P, I32, P, P, P, I32],
+        "pwa_nll_batch_async": [P, I32, P, P, I32],
         "pwa_last_flags": [P, ctypes.POINTER(ctypes.c_uint32)],
         "pwa_layout_ld": [P, I32, ctypes.POINTER(I64)],
         "pwa_set_timing": [P, ctypes.c_int],
@@ -290,6 +292,19 @@ class Context:
         g = np.zeros_like(v) if grad else None
         self._check(self.lib.pwa_nll_batch(self.h, nv, _ptr(v), _ptr(nll), _ptr(g), int(split)))
         return (nll, g) if grad else nll
+
+    def nll_batch_async(self, V_dev, out_dev, split: int = 2):
+        """V_dev: torch cuda float64 [nv, 2k] contiguous; out_dev: torch cuda float64
+        [nv, 2k + 2] contiguous (per vector: nll, grad[2k], flags).  Enqueued on
+        the context's stream; a synchronous nll_batch with at least nv vectors and
+        the same split must have prepared the workspace."""
+        nv = V_dev.shape[0]
+        if not (V_dev.is_contiguous() and out_dev.is_contiguous()):
+            raise ValueError("V_dev and out_dev must be contiguous")
+        if V_dev.shape[1] != 2 * self.k or tuple(out_dev.shape) != (nv, 2 * self.k + 2):
+            raise ValueError("V_dev must be [nv, 2k] and out_dev [nv, 2k + 2]")
+        self._check(self.lib.pwa_nll_batch_async(self.h, nv, ctypes.c_void_p(V_dev.data_ptr()),
+                                                 ctypes.c_void_p(out_dev.data_ptr()), int(split)))
 
     def batch_fit(self, V0, iters: int):
         """L-BFGS from every row of V0 [nv, k] (complex) at once; returns

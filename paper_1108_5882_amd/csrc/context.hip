@@ -75,6 +75,7 @@ struct pwa_ctx {
 
     // batched (many-V) path: per-wave FP16 scales of the amplitudes, device scratch
     bool amax_valid = false;
+    bool ascale_dev_valid = false;   // b_ascale holds the current ascale
     std::vector<float> ascale;
     void *b_wfrag = nullptr, *b_ascale = nullptr, *b_vscale = nullptr, *b_V = nullptr;
     void *b_partials = nullptr, *b_out = nullptr;
@@ -320,12 +321,26 @@ pwa_status ensure_amax(pwa_ctx *ctx) {
         ctx->ascale[2 * a] = ctx->ascale[2 * a + 1] = sc;
     }
     ctx->amax_valid = true;
+    ctx->ascale_dev_valid = false;
     return PWA_OK;
 }
 
 // Common set-up of a batched matrix-core pass: state checks, MC matrix,
 // amplitude scales and the argument block (V and out left to the caller).
-pwa_status batch_setup(pwa_ctx *ctx, int32_t nv, BatchArgs &a, int *gpad) {
+// Workspace of at least `bytes`: grown when `alloc`, otherwise PWA_E_STATE if short
+// (the asynchronous entry point allocates nothing).
+pwa_status reserve(pwa_ctx *ctx, bool alloc, void **buf, size_t *cap, size_t bytes, const char *what) {
+    if (*cap >= bytes) return PWA_OK;
+    if (!alloc)
+        return fail(ctx, PWA_E_STATE, "workspace too small (%s): call pwa_nll_batch with at least as many "
+                    "vectors and the same split first", what);
+    return grow(ctx, buf, cap, bytes, what);
+}
+
+// Arguments of the batched pass for nv vectors.  With alloc = false nothing is
+// allocated, launched or waited for: every lazily built input (Gram matrix,
+// operand scales) and every workspace must already exist.
+pwa_status batch_setup(pwa_ctx *ctx, int32_t nv, BatchArgs &a, int *gpad, bool alloc = true) {
     const int k = ctx->k;
     if (!ctx->s[0].set) return fail(ctx, PWA_E_STATE, "data sample not set");
     const int64_t nd = ctx->s[0].n;
@@ -335,6 +350,8 @@ pwa_status batch_setup(pwa_ctx *ctx, int32_t nv, BatchArgs &a, int *gpad) {
         return fail(ctx, PWA_E_STATE, "MC sample is empty: no normalisation");
     const bool gram = ctx->mode == PWA_MC_GRAM && need_mc;
     pwa_status st;
+    if (!alloc && ((gram && !ctx->gram_valid) || !ctx->amax_valid || !ctx->ascale_dev_valid))
+        return fail(ctx, PWA_E_STATE, "batched inputs not prepared: call pwa_nll_batch once first");
     if (gram && (st = ensure_gram(ctx)) != PWA_OK) return st;
     if ((st = ensure_amax(ctx)) != PWA_OK) return st;
     std::memset(&a, 0, sizeof a);
@@ -357,16 +374,22 @@ pwa_status batch_setup(pwa_ctx *ctx, int32_t nv, BatchArgs &a, int *gpad) {
     const int ngroups = batch_vector_groups(nv, k);
     *gpad = (ngroups + kBatchWaves - 1) / kBatchWaves * kBatchWaves;
     const int k2 = 32 * batch_ks(k);
-    if ((st = grow(ctx, &ctx->b_wfrag, &ctx->b_cap[0],
-                   sizeof(_Float16) * (size_t)*gpad * 2 * batch_ct(k) * batch_ks(k) * 64 * 8, "hipMalloc(weights)")) ||
-        (st = grow(ctx, &ctx->b_ascale, &ctx->b_cap[1], sizeof(float) * k2, "hipMalloc(scales)")) ||
-        (st = grow(ctx, &ctx->b_vscale, &ctx->b_cap[2], sizeof(double) * nv, "hipMalloc(scales)")) ||
-        (st = grow(ctx, &ctx->b_partials, &ctx->b_cap[4],
-                   sizeof(double) * std::max<size_t>(1, batch_partial_doubles(a.n[0], a.n[1], a.tpb, nv, k)),
-                   "hipMalloc(partials)")))
+    const void *ascale_before = ctx->b_ascale;
+    if ((st = reserve(ctx, alloc, &ctx->b_wfrag, &ctx->b_cap[0],
+                      sizeof(_Float16) * (size_t)*gpad * 2 * batch_ct(k) * batch_ks(k) * 64 * 8, "weights")) ||
+        (st = reserve(ctx, alloc, &ctx->b_ascale, &ctx->b_cap[1], sizeof(float) * k2, "scales")) ||
+        (st = reserve(ctx, alloc, &ctx->b_vscale, &ctx->b_cap[2], sizeof(double) * nv, "vector scales")) ||
+        (st = reserve(ctx, alloc, &ctx->b_partials, &ctx->b_cap[4],
+                      sizeof(double) * std::max<size_t>(1, batch_partial_doubles(a.n[0], a.n[1], a.tpb, nv, k)),
+                      "partials")))
         return st;
-    PWA_HIP(ctx, hipMemcpyAsync(ctx->b_ascale, ctx->ascale.data(), sizeof(float) * k2, hipMemcpyHostToDevice,
-                                ctx->stream), "hipMemcpyAsync(scales)");
+    if (ctx->b_ascale != ascale_before) ctx->ascale_dev_valid = false;
+    if (!ctx->ascale_dev_valid) {
+        PWA_HIP(ctx, hipMemcpyAsync(ctx->b_ascale, ctx->ascale.data(), sizeof(float) * k2, hipMemcpyHostToDevice,
+                                    ctx->stream), "hipMemcpyAsync(scales)");
+        PWA_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        ctx->ascale_dev_valid = true;
+    }
     a.ngroups_pad = *gpad;
     // c^2 of the flag test: 1/1024, lowered to 4 / N_D for larger samples (the
     // gradient scale grows with N_D while one event's error does not, so the
@@ -382,24 +405,22 @@ pwa_status batch_setup(pwa_ctx *ctx, int32_t nv, BatchArgs &a, int *gpad) {
 // Batched NLL (and gradient) of nv host vectors on the matrix cores: device
 // weights from V, the matrix-core pass (with refine: flags for data events with
 // small coherent sums, then their exact terms), the per-vector combine.
-pwa_status batch_mfma(pwa_ctx *ctx, int32_t nv, const double *V, double *nll, double *grad, bool refine) {
-    DeviceGuard dg(ctx->device);
+// Enqueues the matrix-core pass for nv vectors read from V_dev (device, nv x 2k)
+// and writes [nll, grad[2k], flags] per vector to out_dev (device).  With
+// alloc = false it allocates, uploads and waits for nothing (see batch_setup).
+pwa_status batch_launch(pwa_ctx *ctx, int32_t nv, const double *V_dev, double *out_dev, bool refine, bool alloc) {
     const int k = ctx->k;
     BatchArgs a;
     int gpad = 0;
-    pwa_status st = batch_setup(ctx, nv, a, &gpad);
+    pwa_status st = batch_setup(ctx, nv, a, &gpad, alloc);
     if (st != PWA_OK) return st;
-    const size_t out_doubles = (size_t)nv * (2 * k + 2);
-    if ((st = grow(ctx, &ctx->b_V, &ctx->b_cap[3], sizeof(double) * 2 * k * (size_t)nv, "hipMalloc(V)")) ||
-        (st = grow(ctx, &ctx->b_out, &ctx->b_cap[5], sizeof(double) * out_doubles, "hipMalloc(out)")))
-        return st;
-    PWA_HIP(ctx, hipMemcpyAsync(ctx->b_V, V, sizeof(double) * 2 * k * (size_t)nv, hipMemcpyHostToDevice,
-                                ctx->stream), "hipMemcpyAsync(V)");
-    a.V = static_cast<const double *>(ctx->b_V);
+    a.V = V_dev;
     a.vstride = 2 * k;
-    a.out = static_cast<double *>(ctx->b_out);
+    a.out = out_dev;
     a.ostride = 2 * k + 2;
     if (refine && a.n[0] > 0) {
+        if (!alloc && !ctx->rnorm_valid)
+            return fail(ctx, PWA_E_STATE, "row norms not prepared: call pwa_nll_batch with split 3 first");
         if (!ctx->rnorm_valid) {
             if (ctx->b_rnorm) (void)hipFree(ctx->b_rnorm);
             ctx->b_rnorm = nullptr;
@@ -407,8 +428,8 @@ pwa_status batch_mfma(pwa_ctx *ctx, int32_t nv, const double *V, double *nll, do
             PWA_HIP(ctx, launch_rownorm(a.A[0], a.n[0], a.ld, k, ctx->b_rnorm, ctx->stream), "row norm launch");
             ctx->rnorm_valid = true;
         }
-        if ((st = grow(ctx, &ctx->b_flags, &ctx->flags_cap,
-                       sizeof(unsigned long long) * batch_flag_words(a.n[0], nv, k), "hipMalloc(flags)")))
+        if ((st = reserve(ctx, alloc, &ctx->b_flags, &ctx->flags_cap,
+                          sizeof(unsigned long long) * batch_flag_words(a.n[0], nv, k), "flags")))
             return st;
         a.rnorm = ctx->b_rnorm;
         a.flags = static_cast<unsigned long long *>(ctx->b_flags);
@@ -418,7 +439,7 @@ pwa_status batch_mfma(pwa_ctx *ctx, int32_t nv, const double *V, double *nll, do
     hipError_t e = launch_batch_weights(a, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "batched weights launch");
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (ctx->timing) {
+    if (ctx->timing && alloc) {
         PWA_HIP(ctx, hipEventCreate(&e0), "hipEventCreate");
         PWA_HIP(ctx, hipEventCreate(&e1), "hipEventCreate");
         PWA_HIP(ctx, hipEventRecord(e0, ctx->stream), "hipEventRecord");
@@ -427,12 +448,28 @@ pwa_status batch_mfma(pwa_ctx *ctx, int32_t nv, const double *V, double *nll, do
     if (e != hipSuccess) return hip_fail(ctx, e, "batched kernel launch");
     if (refine && (e = launch_batch_refine(a, ctx->stream)) != hipSuccess)
         return hip_fail(ctx, e, "refinement launch");
-    if (ctx->timing) {
+    if (e0) {
         PWA_HIP(ctx, hipEventRecord(e1, ctx->stream), "hipEventRecord");
         ctx->batch_events.emplace_back(e0, e1);
     }
     e = launch_batch_combine(a, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "batched combine launch");
+    return PWA_OK;
+}
+
+pwa_status batch_mfma(pwa_ctx *ctx, int32_t nv, const double *V, double *nll, double *grad, bool refine) {
+    DeviceGuard dg(ctx->device);
+    const int k = ctx->k;
+    const size_t out_doubles = (size_t)nv * (2 * k + 2);
+    pwa_status st;
+    if ((st = grow(ctx, &ctx->b_V, &ctx->b_cap[3], sizeof(double) * 2 * k * (size_t)nv, "hipMalloc(V)")) ||
+        (st = grow(ctx, &ctx->b_out, &ctx->b_cap[5], sizeof(double) * out_doubles, "hipMalloc(out)")))
+        return st;
+    PWA_HIP(ctx, hipMemcpyAsync(ctx->b_V, V, sizeof(double) * 2 * k * (size_t)nv, hipMemcpyHostToDevice,
+                                ctx->stream), "hipMemcpyAsync(V)");
+    if ((st = batch_launch(ctx, nv, static_cast<const double *>(ctx->b_V), static_cast<double *>(ctx->b_out),
+                           refine, true)) != PWA_OK)
+        return st;
     std::vector<double> out(out_doubles);
     PWA_HIP(ctx, hipMemcpyAsync(out.data(), ctx->b_out, sizeof(double) * out_doubles, hipMemcpyDeviceToHost,
                                 ctx->stream), "hipMemcpyAsync(result)");
@@ -753,6 +790,26 @@ pwa_status pwa_nll_batch(pwa_ctx *ctx, int32_t nv, const double *V, double *nll,
         return domain ? fail(ctx, PWA_E_DOMAIN, "non-positive intensity or normalisation") : PWA_OK;
     }
     return batch_mfma(ctx, nv, V, nll, grad, split == 3);
+}
+
+pwa_status pwa_nll_batch_async(pwa_ctx *ctx, int32_t nv, const double *V_dev, double *out_dev, int32_t split) {
+    if (!ctx) return fail(nullptr, PWA_E_INVAL, "null context");
+    if (nv < 0 || (nv > 0 && (!V_dev || !out_dev))) return fail(ctx, PWA_E_INVAL, "bad batch arguments");
+    if (split != 0 && split != 2 && split != 3)
+        return fail(ctx, PWA_E_UNSUPPORTED, "split %d not available", split);
+    if (split >= 2 && ctx->prec != PWA_F32)
+        return fail(ctx, PWA_E_UNSUPPORTED, "the matrix-core path needs an FP32 context");
+    if (nv == 0) return PWA_OK;
+    const int k = ctx->k;
+    if (split == 0) {
+        for (int32_t b = 0; b < nv; ++b) {
+            pwa_status st = pwa_nll_grad_async(ctx, V_dev + (size_t)b * 2 * k, out_dev + (size_t)b * (2 * k + 2));
+            if (st != PWA_OK) return st;
+        }
+        return PWA_OK;
+    }
+    DeviceGuard dg(ctx->device);
+    return batch_launch(ctx, nv, V_dev, out_dev, split == 3, false);
 }
 
 pwa_status pwa_last_flags(pwa_ctx *ctx, uint32_t *flags) {
