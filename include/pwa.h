@@ -175,6 +175,20 @@ pwa_status pwa_nll_batch(pwa_ctx *ctx, int32_t nv, const double *V, double *nll,
 pwa_status pwa_nll_batch_async(pwa_ctx *ctx, int32_t nv, const double *V_dev, double *out_dev,
                                int32_t split);
 
+/* Hessian of the NLL in the real parameters at V: the matrix whose inverse is
+ * the fit's error matrix (Section 4 on the cost of error calculations).
+ *   V   host, 2k doubles (Re V_a, Im V_a interleaved, as for the gradient)
+ *   H   host, 2k x 2k doubles, row-major: H[m * 2k + n] = d2 NLL / dx_m dx_n
+ *       with x_{2a} = Re V_a, x_{2a+1} = Im V_a; symmetric.
+ * Eq. 2 or Eq. 3 form as set by pwa_set_mc_mode.  One pass over the data rows
+ * (per event the second derivative of 2 Re ln z_i: the complex symmetric
+ * sum_i A_ia A_ic / z_i^2, FP64 from the stored amplitudes) plus the MC matrix
+ * of Eq. 3 (built once per MC sample, as in PWA_MC_GRAM mode) for the
+ * normalisation term.  Synchronous; allocates workspace on first use.
+ * Errors: PWA_E_INVAL, PWA_E_STATE (a sample missing), PWA_E_DOMAIN (a data
+ * event with z = 0, or S <= 0; H then holds non-finite values), PWA_E_HIP. */
+pwa_status pwa_hessian(pwa_ctx *ctx, const double *V, double *H);
+
 /* Minimise the NLL from nv starting vectors at once on the context's samples
  * (multi-start, Section 2): every iteration evaluates all trial vectors with
  * the matrix-core pass of pwa_nll_batch (split 2) and advances one device

@@ -25,7 +25,7 @@ MAX_K = 64
 # every entry point declared in include/pwa.h
 EXPORTS = [
     "pwa_create", "pwa_destroy", "pwa_set_amplitudes", "pwa_set_mc_mode", "pwa_nll",
-    "pwa_nll_grad", "pwa_nll_grad_async", "pwa_nll_batch", "pwa_nll_batch_async", "pwa_last_flags",
+    "pwa_nll_grad", "pwa_nll_grad_async", "pwa_nll_batch", "pwa_nll_batch_async", "pwa_hessian", "pwa_last_flags",
     "pwa_last_error",
     "pwa_layout_ld", "pwa_set_timing", "pwa_kernel_time", "pwa_get_stream_cfg",
     "pwa_set_stream_cfg", "pwa_autotune", "pwa_batch_kernel_time",
@@ -107,6 +107,7 @@ def load(path: str = LIB_PATH):
         "pwa_nll_grad_async": [P, P, P],
         "pwa_nll_batch": [P, I32, P, P, P, I32],
         "pwa_nll_batch_async": [P, I32, P, P, I32],
+        "pwa_hessian": [P, P, P],
         "pwa_last_flags": [P, ctypes.POINTER(ctypes.c_uint32)],
         "pwa_layout_ld": [P, I32, ctypes.POINTER(I64)],
         "pwa_set_timing": [P, ctypes.c_int],
@@ -292,6 +293,19 @@ class Context:
         g = np.zeros_like(v) if grad else None
         self._check(self.lib.pwa_nll_batch(self.h, nv, _ptr(v), _ptr(nll), _ptr(g), int(split)))
         return (nll, g) if grad else nll
+
+    def hessian(self, V):
+        """2k x 2k Hessian of the NLL at V ([k] complex or [2k] real) in the real
+        parameters (Re V_a, Im V_a interleaved)."""
+        V = np.asarray(V)
+        if np.iscomplexobj(V):
+            v = np.empty(2 * V.shape[0])
+            v[0::2], v[1::2] = V.real, V.imag
+        else:
+            v = np.ascontiguousarray(V, dtype=np.float64).ravel()
+        H = np.zeros((v.shape[0], v.shape[0]))
+        self._check(self.lib.pwa_hessian(self.h, _ptr(v), _ptr(H)))
+        return H
 
     def nll_batch_async(self, V_dev, out_dev, split: int = 2):
         """V_dev: torch cuda float64 [nv, 2k] contiguous; out_dev: torch cuda float64

@@ -86,6 +86,9 @@ struct pwa_ctx {
     float *b_rnorm = nullptr;
     void *b_flags = nullptr;
     size_t flags_cap = 0;
+    // Hessian: block partials, T, V, H and a status word
+    void *h_buf = nullptr;
+    size_t h_cap = 0;
 
     std::string err;
 };
@@ -659,7 +662,7 @@ pwa_status pwa_destroy(pwa_ctx *ctx) {
         }
     if (ctx->gram) (void)hipFree(ctx->gram);
     for (void *b : {ctx->b_wfrag, ctx->b_ascale, ctx->b_vscale, ctx->b_V, ctx->b_partials, ctx->b_out,
-                    (void *)ctx->b_amax, (void *)ctx->b_rnorm, ctx->b_flags})
+                    (void *)ctx->b_amax, (void *)ctx->b_rnorm, ctx->b_flags, ctx->h_buf})
         if (b) (void)hipFree(b);
     if (ctx->partials) (void)hipFree(ctx->partials);
     if (ctx->out_dev) (void)hipFree(ctx->out_dev);
@@ -810,6 +813,44 @@ pwa_status pwa_nll_batch_async(pwa_ctx *ctx, int32_t nv, const double *V_dev, do
     }
     DeviceGuard dg(ctx->device);
     return batch_launch(ctx, nv, V_dev, out_dev, split == 3, false);
+}
+
+pwa_status pwa_hessian(pwa_ctx *ctx, const double *V, double *H) {
+    if (!ctx) return fail(nullptr, PWA_E_INVAL, "null context");
+    if (!V || !H) return fail(ctx, PWA_E_INVAL, "null argument");
+    if (!ctx->s[0].set) return fail(ctx, PWA_E_STATE, "data sample not set");
+    const int k = ctx->k;
+    for (int i = 0; i < 2 * k; ++i)
+        if (!std::isfinite(V[i])) return fail(ctx, PWA_E_INVAL, "V is not finite");
+    DeviceGuard dg(ctx->device);
+    const int64_t nd = ctx->s[0].n;
+    const bool need_mc = ctx->extended || nd > 0;
+    if (need_mc && !ctx->s[1].set) return fail(ctx, PWA_E_STATE, "MC sample not set");
+    if (need_mc && ctx->s[1].n == 0 && nd > 0) return fail(ctx, PWA_E_STATE, "MC sample is empty: no normalisation");
+    pwa_status st;
+    if (need_mc && (st = ensure_gram(ctx)) != PWA_OK) return st;
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ctx->cu_count * 2, (nd + 63) / 64));
+    const size_t n_part = hessian_partial_doubles(k, blocks), n_t = 2 * (size_t)k * k, n_v = 2 * (size_t)k,
+                 n_h = 4 * (size_t)k * k + 1;
+    const size_t doubles = n_part + n_t + n_v + n_h + 1;
+    if ((st = grow(ctx, &ctx->h_buf, &ctx->h_cap, sizeof(double) * doubles, "hipMalloc(hessian)"))) return st;
+    double *part = static_cast<double *>(ctx->h_buf);
+    double *Tm = part + n_part, *Vd = Tm + n_t, *Hd = Vd + n_v;
+    unsigned *flag = reinterpret_cast<unsigned *>(Hd + n_h);
+    PWA_HIP(ctx, hipMemcpyAsync(Vd, V, sizeof(double) * n_v, hipMemcpyHostToDevice, ctx->stream),
+            "hipMemcpyAsync(V)");
+    // without MC rows (Eq. 2 form, no data) the normalisation term is absent: T (zero) stands in for M
+    const double *M = need_mc ? ctx->gram : Tm;
+    hipError_t e = launch_hessian(ctx->prec, ctx->s[0].A, nd, ctx->ld, k, Vd, M, (double)nd, ctx->extended, part,
+                                  blocks, Tm, flag, Hd, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hessian launch");
+    std::vector<double> h(n_h);
+    PWA_HIP(ctx, hipMemcpyAsync(h.data(), Hd, sizeof(double) * n_h, hipMemcpyDeviceToHost, ctx->stream),
+            "hipMemcpyAsync(H)");
+    PWA_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    std::copy(h.begin(), h.end() - 1, H);
+    ctx->last_flags = h.back() != 0.0 ? 1u : 0u;
+    return ctx->last_flags ? fail(ctx, PWA_E_DOMAIN, "zero coherent sum or non-positive normalisation") : PWA_OK;
 }
 
 pwa_status pwa_last_flags(pwa_ctx *ctx, uint32_t *flags) {

@@ -199,6 +199,17 @@ hipError_t launch_gram(pwa_prec prec, const void *A, const void *w, int64_t n, i
                        double n_gen, double *partials, int blocks, double *M, hipStream_t stream);
 size_t gram_partial_doubles(int k, int blocks);
 
+// Hessian of the NLL in the real parameters (hessian.hip): one pass over the n
+// data rows (A, row stride ld complex) at V_dev (2k doubles, device) with the
+// MC matrix M (k x k complex, FP64, 1/N_gen folded in), nd data events and the
+// likelihood form; writes H (2k x 2k row-major, then one status double: 0 ok,
+// 1 domain failure).  partials: hessian_partial_doubles(k, blocks) doubles;
+// Tm: 2 k^2 doubles; flag: one unsigned.
+hipError_t launch_hessian(pwa_prec prec, const void *A, int64_t n, int64_t ld, int k, const double *V_dev,
+                          const double *M, double nd, int extended, double *partials, int blocks, double *Tm,
+                          unsigned *flag, double *H, hipStream_t stream);
+size_t hessian_partial_doubles(int k, int blocks);
+
 // ---------------------------------------------------------------- surrogate MLP
 // Device buffers of the in -> hidden -> hidden -> 1 network (FP32 master
 // parameters P in the layout [W1 hidden x in][b1][W2 hidden x hidden][b2][w3][b3]).
