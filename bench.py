@@ -80,8 +80,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--extras", default="batched,surrogate",
-                    help="comma list of batched, surrogate, multifit (or none)")
+    ap.add_argument("--extras", default="batched,surrogate,hessian",
+                    help="comma list of batched, surrogate, hessian, multifit (or none)")
     ap.add_argument("--probe", action="store_true",
                     help="for HBM counter runs: a few evaluations plus a plain device copy of the "
                          "same byte count (the counter scale reference); prints no JSON")
@@ -175,6 +175,8 @@ def main():
         rec["cpu_baseline"] = cpu_baseline(s, V, args.cpu_seconds)
     extras = [e for e in args.extras.split(",") if e and e != "none"]
     rec["extras"] = {}
+    if "hessian" in extras:
+        rec["extras"]["hessian"] = extra_hessian(ctx, V, nd, k)
     if "surrogate" in extras:
         rec["extras"]["surrogate"] = extra_surrogate(ctx, k)
     ctx.close()
@@ -344,6 +346,32 @@ def extra_surrogate(ctx, k: int, n_train: int = 100000, n_screen: int = 100000, 
     }
     log(f"surrogate: {json.dumps(out)}")
     return out
+
+
+FP64_PEAK_TFS = 78.6         # FP64 vector peak of the MI355X
+
+
+def extra_hessian(ctx, V, nd: int, k: int, reps: int = 20):
+    """The NLL Hessian (error matrix) on the single-V sample: one pass over the
+    data rows plus the MC matrix (built once), synchronous calls."""
+    import numpy as np
+    for _ in range(3):
+        H = ctx.hessian(V)
+    w0 = time.perf_counter()
+    for _ in range(reps):
+        H = ctx.hessian(V)
+    ms = (time.perf_counter() - w0) / reps * 1e3
+    # per data event: A_a A_c (6 flops) times 1 / z^2 (6 flops) for each of the
+    # k (k + 1) / 2 distinct entries of the symmetric T, plus z and 1 / z^2
+    alg_flops = nd * (12.0 * k * (k + 1) / 2 + 8.0 * k + 12.0)
+    log(f"hessian: {ms:.3f} ms per call ({nd} data rows, K={k})")
+    return {"workload": f"NLL Hessian (2K x 2K) at one V, K={k}, {nd} data rows, MC by the Gram matrix",
+            "ms_per_call": ms, "symmetric_max_abs_diff": float(np.max(np.abs(H - H.T))),
+            "roofline": {"bound": "alu", "achieved": alg_flops / (ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFS,
+                         "unit": "TFLOP/s", "frac": alg_flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFS,
+                         "traffic": None, "kernel": "hess_partial_kernel (FP64) + finish + assembly",
+                         "alg_flops_per_call": alg_flops,
+                         "note": "wall time of the synchronous call (V upload, kernels, 2K x 2K readback)"}}
 
 
 def extra_multifit(steps: int = 50):

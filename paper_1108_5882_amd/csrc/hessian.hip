@@ -23,98 +23,196 @@ namespace {
 
 constexpr int kHThreads = 256;
 constexpr int kHRows = 32;
-constexpr int kHMaxPer = (PWA_MAX_K * PWA_MAX_K + kHThreads - 1) / kHThreads;
+constexpr int kHMaxTiles = 3;     // 2 x 2 entry tiles per thread (k = 64: 528 tiles over 256 threads)
 
 __global__ void hess_clear_kernel(unsigned *flag) { *flag = 0u; }
 
+// Upper-triangle 2 x 2 tile t -> (ta, tc), ta <= tc, of nt tile rows (row-major order).
+__device__ __forceinline__ void tile_index(int t, int nt, int &ta, int &tc) {
+    int a = 0, row = nt;
+    while (t >= row) {
+        t -= row;
+        ++a;
+        --row;
+    }
+    ta = a;
+    tc = a + t;
+}
+
+// T is complex symmetric: each thread accumulates 2 x 2 tiles (ta, tc) of the
+// upper triangle (rows 2 ta, 2 ta + 1, columns 2 tc, 2 tc + 1).  With fewer
+// tiles than threads the block forms RG = 256 / ntile row groups that take every
+// RG-th row of the LDS tile; the groups' sums are added in group order at the
+// end.  z comes from 8 lanes per row.
 template <typename T>
 __global__ __launch_bounds__(kHThreads) void hess_partial_kernel(const T *__restrict__ A, int64_t n, int64_t ld,
                                                                  int k, const double *__restrict__ V,
                                                                  double *__restrict__ partials,
                                                                  unsigned *__restrict__ flag) {
-    __shared__ double tile[kHRows][2 * PWA_MAX_K];
-    __shared__ double cw[kHRows][2];          // 1 / z^2 per row (0 for absent rows)
+    __shared__ __attribute__((aligned(16))) double tile[kHRows][2 * PWA_MAX_K + 4];
+    __shared__ __attribute__((aligned(16))) double cw[kHRows][2];   // 1 / z^2 per row (0 for absent rows)
+    __shared__ double red[kHThreads][8];              // row-group sums (one tile per slot then)
     const int tid = threadIdx.x;
+    const int nt = (k + 1) / 2;                       // tile rows
+    const int ntile = nt * (nt + 1) / 2;
+    const int S = ntile < kHThreads ? ntile : kHThreads;   // tile slots per row group
+    const int RG = kHThreads / S;                     // row groups (threads past RG S idle)
+    const int rg = tid / S, slot = tid % S;
     const int kk = k * k;
     const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
     const int64_t r0 = (int64_t)blockIdx.x * chunk;
     const int64_t r1 = r0 + chunk < n ? r0 + chunk : n;
 
-    double accr[kHMaxPer], acci[kHMaxPer];
+    int tA[kHMaxTiles], tC[kHMaxTiles];
 #pragma unroll
-    for (int m = 0; m < kHMaxPer; ++m) accr[m] = acci[m] = 0.0;
+    for (int m = 0; m < kHMaxTiles; ++m) {
+        const int t = slot + m * S;
+        tA[m] = tC[m] = -1;
+        if (rg < RG && t < ntile) tile_index(t, nt, tA[m], tC[m]);
+    }
+    double acc[kHMaxTiles][8];                         // (re, im) of entries 00, 01, 10, 11
+#pragma unroll
+    for (int m = 0; m < kHMaxTiles; ++m)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[m][q] = 0.0;
     bool bad = false;
 
+    // the next tile's values are loaded into registers while the current one is used
+    constexpr int kPre = kHRows * 2 * PWA_MAX_K / kHThreads;
+    T pre[kPre];
+    const int width = 4 * nt;                          // staged columns (zero beyond 2k)
+    auto fetch = [&](int64_t b) {
+        const int rws = (int)(r1 - b < kHRows ? r1 - b : kHRows);
+#pragma unroll
+        for (int i = 0; i < kPre; ++i) {
+            const int idx = tid + i * kHThreads;
+            const int r = idx / width, q = idx % width;
+            pre[i] = (idx < kHRows * width && r < rws && q < 2 * k) ? A[2 * (b + r) * ld + q] : T(0);
+        }
+    };
+    if (r0 < r1) fetch(r0);
     for (int64_t base = r0; base < r1; base += kHRows) {
         const int rows = (int)(r1 - base < kHRows ? r1 - base : kHRows);
         __syncthreads();
-        for (int idx = tid; idx < kHRows * 2 * k; idx += kHThreads) {
-            const int r = idx / (2 * k), q = idx % (2 * k);
-            tile[r][q] = r < rows ? (double)A[2 * (base + r) * ld + q] : 0.0;
+        // rows as FP64, zero beyond k (an odd k's last tile reads one zero column)
+#pragma unroll
+        for (int i = 0; i < kPre; ++i) {
+            const int idx = tid + i * kHThreads;
+            if (idx < kHRows * width) tile[idx / width][idx % width] = (double)pre[i];
         }
         __syncthreads();
-        if (tid < kHRows) {
-            double wr = 0.0, wi = 0.0;
-            if (tid < rows) {
-                double zr = 0.0, zi = 0.0;
-                for (int a = 0; a < k; ++a) {
-                    const double ar = tile[tid][2 * a], ai = tile[tid][2 * a + 1];
+        if (base + kHRows < r1) fetch(base + kHRows);
+        {
+            // z of row tid / 8 from 8 lanes (waves sub, sub + 8, ...), summed over the lanes
+            const int row = tid >> 3, sub = tid & 7;
+            double zr = 0.0, zi = 0.0;
+            if (row < rows)
+                for (int a = sub; a < k; a += 8) {
+                    const double ar = tile[row][2 * a], ai = tile[row][2 * a + 1];
                     zr = fma(V[2 * a], ar, fma(-V[2 * a + 1], ai, zr));
                     zi = fma(V[2 * a], ai, fma(V[2 * a + 1], ar, zi));
                 }
-                const double I = zr * zr + zi * zi;
-                if (I > 0.0 && isfinite(I)) {
-                    // 1 / z^2 = conj(z)^2 / I^2
-                    const double i2 = 1.0 / (I * I);
-                    wr = (zr * zr - zi * zi) * i2;
-                    wi = -2.0 * zr * zi * i2;
-                } else {
-                    bad = true;
-                }
+#pragma unroll
+            for (int off = 1; off < 8; off <<= 1) {
+                zr += __shfl_xor(zr, off);
+                zi += __shfl_xor(zi, off);
             }
-            cw[tid][0] = wr;
-            cw[tid][1] = wi;
+            if (sub == 0) {
+                double wr = 0.0, wi = 0.0;
+                if (row < rows) {
+                    const double I = zr * zr + zi * zi;
+                    if (I > 0.0 && isfinite(I)) {
+                        // 1 / z^2 = conj(z)^2 / I^2
+                        const double i2 = 1.0 / (I * I);
+                        wr = (zr * zr - zi * zi) * i2;
+                        wi = -2.0 * zr * zi * i2;
+                    } else {
+                        bad = true;
+                    }
+                }
+                cw[row][0] = wr;
+                cw[row][1] = wi;
+            }
         }
         __syncthreads();
 #pragma unroll
-        for (int m = 0; m < kHMaxPer; ++m) {
-            const int e = tid + m * kHThreads;
-            if (e >= kk) break;
-            const int a = e / k, c = e % k;
-            double sr = accr[m], si = acci[m];
-            for (int r = 0; r < rows; ++r) {
-                const double ar = tile[r][2 * a], ai = tile[r][2 * a + 1];
-                const double br = tile[r][2 * c], bi = tile[r][2 * c + 1];
-                // A_a A_c, then times 1 / z^2
-                const double pr = fma(ar, br, -(ai * bi));
-                const double pi = fma(ar, bi, ai * br);
-                sr = fma(pr, cw[r][0], fma(-pi, cw[r][1], sr));
-                si = fma(pr, cw[r][1], fma(pi, cw[r][0], si));
+        for (int m = 0; m < kHMaxTiles; ++m) {
+            if (tA[m] < 0) continue;
+            const int a0 = 2 * tA[m], c0 = 2 * tC[m];
+            double s[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s[q] = acc[m][q];
+            for (int r = rg; r < rows; r += RG) {
+                const double wr = cw[r][0], wi = cw[r][1];
+                const double x0r = tile[r][2 * a0], x0i = tile[r][2 * a0 + 1];
+                const double x1r = tile[r][2 * a0 + 2], x1i = tile[r][2 * a0 + 3];
+                const double y0r = tile[r][2 * c0], y0i = tile[r][2 * c0 + 1];
+                const double y1r = tile[r][2 * c0 + 2], y1i = tile[r][2 * c0 + 3];
+                // (w x) then times y, for the four entries
+                const double u0r = fma(wr, x0r, -(wi * x0i)), u0i = fma(wr, x0i, wi * x0r);
+                const double u1r = fma(wr, x1r, -(wi * x1i)), u1i = fma(wr, x1i, wi * x1r);
+                s[0] = fma(u0r, y0r, fma(-u0i, y0i, s[0]));
+                s[1] = fma(u0r, y0i, fma(u0i, y0r, s[1]));
+                s[2] = fma(u0r, y1r, fma(-u0i, y1i, s[2]));
+                s[3] = fma(u0r, y1i, fma(u0i, y1r, s[3]));
+                s[4] = fma(u1r, y0r, fma(-u1i, y0i, s[4]));
+                s[5] = fma(u1r, y0i, fma(u1i, y0r, s[5]));
+                s[6] = fma(u1r, y1r, fma(-u1i, y1i, s[6]));
+                s[7] = fma(u1r, y1i, fma(u1i, y1r, s[7]));
             }
-            accr[m] = sr;
-            acci[m] = si;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[m][q] = s[q];
         }
     }
     if (bad) atomicOr(flag, 1u);
+    // add the row groups in group order; with RG > 1 there are fewer tiles than
+    // slots, so each slot holds only its first tile
+    __syncthreads();
+    if (RG > 1) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) red[tid][q] = acc[0][q];
+        __syncthreads();
+        if (rg == 0) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                double v = red[slot][q];
+                for (int g = 1; g < RG; ++g) v += red[g * S + slot][q];
+                acc[0][q] = v;
+            }
+        }
+    }
+    if (rg != 0) return;
     double *out = partials + (int64_t)blockIdx.x * 2 * kk;
 #pragma unroll
-    for (int m = 0; m < kHMaxPer; ++m) {
-        const int e = tid + m * kHThreads;
-        if (e >= kk) break;
-        out[2 * e] = accr[m];
-        out[2 * e + 1] = acci[m];
+    for (int m = 0; m < kHMaxTiles; ++m) {
+        if (tA[m] < 0) continue;
+#pragma unroll
+        for (int ea = 0; ea < 2; ++ea)
+#pragma unroll
+            for (int ec = 0; ec < 2; ++ec) {
+                const int a = 2 * tA[m] + ea, c = 2 * tC[m] + ec;
+                if (a >= k || c >= k) continue;
+                const double vr = acc[m][4 * ea + 2 * ec], vi = acc[m][4 * ea + 2 * ec + 1];
+                out[2 * (a * k + c)] = vr;
+                out[2 * (a * k + c) + 1] = vi;
+                out[2 * (c * k + a)] = vr;          // T is symmetric
+                out[2 * (c * k + a) + 1] = vi;
+            }
     }
 }
 
-// T = sum of the block partials in block order.
-__global__ void hess_finish_kernel(const double *__restrict__ partials, int nblocks, int k,
-                                   double *__restrict__ Tm) {
+// T = sum of the block partials: one block per entry, fixed-order tree.
+constexpr int kFinThreads = 64;
+__global__ __launch_bounds__(kFinThreads) void hess_finish_kernel(const double *__restrict__ partials, int nblocks,
+                                                                  int k, double *__restrict__ Tm) {
     const int kk2 = 2 * k * k;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < kk2; e += gridDim.x * blockDim.x) {
-        double s = 0.0;
-        for (int b = 0; b < nblocks; ++b) s += partials[(int64_t)b * kk2 + e];
-        Tm[e] = s;
-    }
+    const int e = blockIdx.x;
+    double s = 0.0;
+#pragma unroll 4
+    for (int b = threadIdx.x; b < nblocks; b += kFinThreads) s += partials[(int64_t)b * kk2 + e];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+    if (threadIdx.x == 0) Tm[e] = s;
 }
 
 // One block: H (2k x 2k, row-major) from T, M and V; H[2k * 2k] = status flags.
@@ -193,7 +291,7 @@ hipError_t launch_hessian(pwa_prec prec, const void *A, int64_t n, int64_t ld, i
         blocks = 0;
     }
     const int kk2 = 2 * k * k;
-    hipLaunchKernelGGL(hess_finish_kernel, dim3((kk2 + 255) / 256), dim3(256), 0, stream, partials, blocks, k, Tm);
+    hipLaunchKernelGGL(hess_finish_kernel, dim3(kk2), dim3(kFinThreads), 0, stream, partials, blocks, k, Tm);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(hess_assemble_kernel, dim3(1), dim3(256), 0, stream, Tm, M, V_dev, k, nd, extended, flag, H);
     return hipGetLastError();
