@@ -229,6 +229,29 @@ def pin_permutation(orc):
     assert _rel(g1, g2) < 1e-12
 
 
+def pin_shard_combination(orc):
+    """Events shard (Section 3): raw sums (sum ln I, sum w I, the data and MC gradient
+    sums) of disjoint chunks of the data and MC rows add to those of the whole sample,
+    and the nonlinear combine of the added sums gives the whole-sample NLL and gradient."""
+    Ad, Am, V, w = _small_case(37, nd=301, nm=907, weighted=True)
+    whole_n, whole_g, whole_p = orc.nll_grad(Ad, Am, V, w=w, parts=True)
+    cd, cm = [0, 97, 210, 301], [0, 400, 555, 907]
+    tot = None
+    for i in range(3):
+        _, _, p = orc.nll_grad(Ad[cd[i]:cd[i + 1]], Am[cm[i]:cm[i + 1]], V, w=w[cm[i]:cm[i + 1]],
+                               n_gen=Am.shape[0], parts=True)
+        tot = dict(p) if tot is None else {k: tot[k] + p[k] for k in tot}
+    for key in ("sum_log", "s_raw"):
+        assert abs(tot[key] - whole_p[key]) < 1e-12 * (abs(whole_p[key]) + 1), key
+    for key in ("GD", "HM"):
+        assert _rel(tot[key], whole_p[key]) < 1e-12, key
+    nd, ng = Ad.shape[0], Am.shape[0]
+    nll = -tot["sum_log"] + nd * np.log(tot["s_raw"] / ng)
+    grad = 2 * (-tot["GD"] + nd / tot["s_raw"] * tot["HM"])
+    assert abs(nll - whole_n) < 1e-12 * (abs(whole_n) + nd)
+    assert _rel(grad, whole_g) < 1e-11
+
+
 # ---------------------------------------------------------- exact arithmetic
 def _frac_c(z):
     return (Fraction(z.real), Fraction(z.imag))
