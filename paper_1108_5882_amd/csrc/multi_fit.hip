@@ -27,9 +27,47 @@ constexpr int kMW = kMT / 64;
 
 // Streams tiles [t0, t1) of one sample with shape (L, C, U); waves take tiles
 // t0 + wave, t0 + wave + kMW, ...; returns the block's partial in red.
-constexpr int kRedSlot = 2 * 3 + 1;      // largest 2C + 1 of the shapes below
+constexpr int kRedSlot = 2 * 6 + 1;      // largest 2C + 1 of the shapes below
 
+// Wave index of lane j's local complex c.  Contiguous (CH = false): lane j
+// holds waves [jC, jC + C).  Chunked (CH = true, C even): lane j holds the
+// 2-wave chunks j, j + L, j + 2L, ..., so each 16-byte load instruction of a
+// lane group covers one contiguous span of the row (used for rows of 24 and
+// 48 waves, which three contiguous waves per lane would read in 8-byte pieces).
+template <int L, int C, bool CH>
+__device__ __forceinline__ int wave_of(int j, int c) {
+    if constexpr (CH) return 2 * (j + L * (c >> 1)) + (c & 1);
+    else return j * C + c;
+}
+
+// Row loads of the chunked layout (same registers as Stage::load fills).
 template <int L, int C, int U, int SEG>
+__device__ __forceinline__ void load_chunked(Stage<float, L, C, U, SEG> &st, const float *__restrict__ A,
+                                             const float *__restrict__ W, int64_t n, int64_t ld, int64_t tile,
+                                             int g, int j) {
+    typedef float f4c __attribute__((ext_vector_type(4)));
+    typedef const f4c __attribute__((address_space(1))) *gp4;
+    constexpr int G = 64 / L;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        int64_t row = tile * (G * U) + (int64_t)u * G + g;
+        row = row < n ? row : n - 1;
+#pragma unroll
+        for (int i = 0; i < C / 2; ++i) {
+            const f4c v = __builtin_nontemporal_load((gp4)(A + 2 * (row * ld + 2 * (j + L * i))));
+            st.a[u][4 * i + 0] = v.x;
+            st.a[u][4 * i + 1] = v.y;
+            st.a[u][4 * i + 2] = v.z;
+            st.a[u][4 * i + 3] = v.w;
+        }
+        if constexpr (SEG == 1) {
+            typedef const float __attribute__((address_space(1))) *gpf;
+            st.w[u] = W ? __builtin_nontemporal_load((gpf)(W + row)) : 1.f;
+        }
+    }
+}
+
+template <int L, int C, int U, int SEG, bool CH = false>
 __device__ void multi_item(const MultiItem &it, const MultiFit &fit, double *slot, double *red) {
     constexpr int SLOT = 2 * C + 1;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -41,23 +79,27 @@ __device__ void multi_item(const MultiItem &it, const MultiFit &fit, double *slo
     double vr[C], vi[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        const int a = j * C + c;
+        const int a = wave_of<L, C, CH>(j, c);
         vr[c] = a < fit.k ? V[2 * a] : 0.0;
         vi[c] = a < fit.k ? V[2 * a + 1] : 0.0;
     }
+    auto ld_stage = [&](Stage<float, L, C, U, SEG> &st, int64_t tt) {
+        if constexpr (CH) load_chunked<L, C, U, SEG>(st, A, W, n, fit.ld, tt, g, j);
+        else st.load(A, W, n, fit.ld, tt, g, j);
+    };
     double acc_t = 0.0, acc_r[C], acc_i[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc_r[c] = acc_i[c] = 0.0;
     int64_t t = it.t0 + wid;
     if (t < it.t1) {
         Stage<float, L, C, U, SEG> s0, s1;
-        s0.load(A, W, n, fit.ld, t, g, j);
+        ld_stage(s0, t);
         for (;;) {
-            s1.load(A, W, n, fit.ld, t + kMW, g, j);
+            ld_stage(s1, t + kMW);
             s0.compute(n, t, g, vr, vi, acc_t, acc_r, acc_i);
             t += kMW;
             if (t >= it.t1) break;
-            s0.load(A, W, n, fit.ld, t + kMW, g, j);
+            ld_stage(s0, t + kMW);
             s1.compute(n, t, g, vr, vi, acc_t, acc_r, acc_i);
             t += kMW;
             if (t >= it.t1) break;
@@ -89,7 +131,16 @@ __device__ void multi_item(const MultiItem &it, const MultiFit &fit, double *slo
             for (int w = 0; w < kMW; ++w) s += R(w, 0, 0);
         } else {
             const int a = (idx - 1) >> 1, q = (idx - 1) & 1;
-            for (int w = 0; w < kMW; ++w) s += R(w, a / C, 1 + 2 * (a % C) + q);
+            // lane and local complex of wave a (inverse of wave_of)
+            int jj, cc;
+            if constexpr (CH) {
+                jj = (a >> 1) % L;
+                cc = 2 * ((a >> 1) / L) + (a & 1);
+            } else {
+                jj = a / C;
+                cc = a % C;
+            }
+            for (int w = 0; w < kMW; ++w) s += R(w, jj, 1 + 2 * cc + q);
         }
         slot[idx] = s;
     }
@@ -104,9 +155,9 @@ __device__ void dispatch_item(const MultiItem &it, const MultiFit &fit, double *
         case 8: multi_item<4, 2, 4, SEG>(it, fit, slot, red); break;
         case 12: multi_item<4, 3, 2, SEG>(it, fit, slot, red); break;
         case 16: multi_item<8, 2, 4, SEG>(it, fit, slot, red); break;
-        case 24: multi_item<8, 3, 2, SEG>(it, fit, slot, red); break;
+        case 24: multi_item<4, 6, 2, SEG, true>(it, fit, slot, red); break;
         case 32: multi_item<16, 2, 4, SEG>(it, fit, slot, red); break;
-        case 48: multi_item<16, 3, 2, SEG>(it, fit, slot, red); break;
+        case 48: multi_item<8, 6, 2, SEG, true>(it, fit, slot, red); break;
         default: break;
     }
 }
@@ -219,9 +270,9 @@ int multi_rows_per_tile(int64_t ld) {
         case 8: return 16 * 4;
         case 12: return 16 * 2;
         case 16: return 8 * 4;
-        case 24: return 8 * 2;
+        case 24: return 16 * 2;
         case 32: return 4 * 4;
-        case 48: return 4 * 2;
+        case 48: return 8 * 2;
         default: return 0;
     }
 }
