@@ -146,7 +146,7 @@ pwa_status pwa_nll_grad_async(pwa_ctx *ctx, const double *V_dev, double *out_dev
  *               error in z / I; the gradient error is stated, not bounded.
  *            3  as 2, but data events with |z| < c |V| |A_i| are left out
  *               of the matrix-core sums, flagged, and their terms recomputed
- *               exactly in FP64 by a second kernel (c^2 = min(1/1024, 4/N_D):
+ *               exactly in FP64 by a second kernel (c^2 = min(1/64, sqrt(k)/N_D):
  *               the gradient scale grows with N_D, one event's error does
  *               not): NLL and gradient of every vector within 1e-6.
  *            Splits 2 and 3 need an FP32 context.

@@ -394,10 +394,12 @@ pwa_status batch_setup(pwa_ctx *ctx, int32_t nv, BatchArgs &a, int *gpad, bool a
         ctx->ascale_dev_valid = true;
     }
     a.ngroups_pad = *gpad;
-    // c^2 of the flag test: 1/1024, lowered to 4 / N_D for larger samples (the
-    // gradient scale grows with N_D while one event's error does not, so the
-    // expected number of events in the flagged region stays constant)
-    a.cthr2 = (float)std::min<double>(kRefineC2, 4.0 / std::max<double>(1.0, (double)nd));
+    // c^2 of the flag test: sqrt(k) / N_D, at most 1/64.  An unflagged event's
+    // error in conj(A) z / I is at most about eps sqrt(k) / c^2 (in units of
+    // 1/|V|) while the gradient scale grows with N_D, so c^2 proportional to
+    // sqrt(k) / N_D keeps every vector within 1e-6 and the expected number of
+    // flagged events bounded as the sample grows
+    a.cthr2 = (float)std::min<double>(kRefineC2, std::sqrt((double)k) / std::max<double>(1.0, (double)nd));
     a.wfrag = ctx->b_wfrag;
     a.ascale = static_cast<const float *>(ctx->b_ascale);
     a.vscale = static_cast<const double *>(ctx->b_vscale);

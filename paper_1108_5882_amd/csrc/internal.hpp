@@ -125,7 +125,7 @@ hipError_t launch_batch(const BatchArgs &args, bool refine, hipStream_t stream);
 hipError_t launch_batch_refine(const BatchArgs &args, hipStream_t stream);
 size_t batch_flag_words(int64_t n0, int nv, int k);
 hipError_t launch_rownorm(const float *A, int64_t n, int64_t ld, int k, float *out, hipStream_t stream);
-constexpr float kRefineC2 = 1.0f / 1024.0f;   // largest c^2 (c = 1/32); batch_setup lowers it for large samples
+constexpr float kRefineC2 = 1.0f / 64.0f;     // largest c^2 (c = 1/8); batch_setup lowers it as sqrt(k) / N_D
 hipError_t launch_batch_combine(const BatchArgs &args, hipStream_t stream);
 // Device-side forward weights from args.V: the per-vector scales, then the
 // FP16 fragments (args.wfrag, sized for the padded vector groups).

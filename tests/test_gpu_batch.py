@@ -13,7 +13,7 @@ vectors meet 1e-6.
 
 Split 3 is split 2 plus an exact treatment of those events: a data event
 whose coherent sum is small against the bound |z| <= |V| |A_i| (|z| < c |V|
-|A_i|, c^2 = min(1/1024, 4/N_D)) is left out of the matrix-core sums, flagged,
+|A_i|, c^2 = min(1/64, sqrt(K)/N_D)) is left out of the matrix-core sums, flagged,
 and recomputed in FP64 by a second kernel; it meets 1e-6 for every vector.  Split 0 (one exact streaming
 pass per vector) meets 1e-6 everywhere and is tested here too.
 """
@@ -147,6 +147,19 @@ def test_batch_full_size_sampled(pwa):
         nll3, grad3 = c.nll_batch(Vs, split=3)
     for b in (0, 77, 199, 255):
         _check(s.A_data, s.A_mc, Vs[b:b + 1], nll3[b:b + 1], grad3[b:b + 1], label=f"full split 3 V{b}")
+
+
+def test_batch_many_vectors_split3(pwa):
+    """2050 vectors (65 vector groups, the last one ragged) in one split-3 pass:
+    flag words and recomputation across many groups, 1e-6 for every vector."""
+    k, nv = 16, 2050
+    s = synth.make_sample(2, n_data=1501, n_mc=4507, k=k, seed=61)
+    Vs = synth.eval_vectors(2, nv, k, seed=61)
+    with pwa.Context(0, "f32") as c:
+        c.set_amplitudes("data", s.A_data)
+        c.set_amplitudes("mc", s.A_mc)
+        nll, grad = c.nll_batch(Vs, split=3)
+    _check(s.A_data, s.A_mc, Vs, nll, grad, label=f"split 3, {nv} vectors")
 
 
 def test_batch_edge_cases(pwa):
