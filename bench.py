@@ -80,7 +80,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--extras", default="batched,surrogate,hessian",
+    ap.add_argument("--extras", default="batched,surrogate,hessian,multifit",
                     help="comma list of batched, surrogate, hessian, multifit (or none)")
     ap.add_argument("--probe", action="store_true",
                     help="for HBM counter runs: a few evaluations plus a plain device copy of the "
