@@ -26,7 +26,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(_HERE, "oracle.c")
 LIB = os.path.join(_HERE, "liboracle.so")
-CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math", "-ffp-contract=off"]
+CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math", "-ffp-contract=off", "-fopenmp"]
 
 
 def build(force: bool = True, src: str = SRC, out: str = LIB) -> str:
@@ -56,7 +56,13 @@ class Oracle:
         lib.orc_nll_grad.argtypes = [I64, P, I64, I64, P, I64, P, D, I32, P, ctypes.c_int, P, P, P]
         lib.orc_gram.argtypes = [I64, P, I64, P, D, I32, P]
         lib.orc_nll_grad_gram.argtypes = [I64, P, I64, I32, P, P, ctypes.c_int, P, P]
-        for f in (lib.orc_intensity, lib.orc_nll_grad, lib.orc_gram, lib.orc_nll_grad_gram):
+        fns = [lib.orc_intensity, lib.orc_nll_grad, lib.orc_gram, lib.orc_nll_grad_gram]
+        self.has_chunked = hasattr(lib, "orc_nll_grad_chunked")
+        if self.has_chunked:
+            lib.orc_nll_grad_chunked.argtypes = [I64, P, I64, I64, P, I64, P, D, I32, P, ctypes.c_int,
+                                                 ctypes.c_int, P, P, P]
+            fns.append(lib.orc_nll_grad_chunked)
+        for f in fns:
             f.restype = ctypes.c_int
         self.lib = lib
         self.path = path
@@ -87,6 +93,27 @@ class Oracle:
         pr = np.zeros(2 + 4 * k)
         if self.lib.orc_nll_grad(Ad.shape[0], _ptr(Ad), k, Am.shape[0], _ptr(Am), k, _ptr(wm), ng,
                                  k, _ptr(V), int(bool(extended)), _ptr(nll), _ptr(grad), _ptr(pr)):
+            raise ValueError("oracle: invalid arguments")
+        if parts:
+            d = dict(sum_log=pr[0], s_raw=pr[1], GD=pr[2:2 + 2 * k].copy(), HM=pr[2 + 2 * k:].copy())
+            return float(nll[0]), grad, d
+        return float(nll[0]), grad
+
+    def nll_grad_chunked(self, A_data, A_mc, V, w=None, n_gen=None, extended=False, threads=0, parts=False):
+        """nll_grad with the events cut into fixed chunks summed on `threads` threads
+        (0: all); the result does not depend on the thread count."""
+        V = _c128(V).ravel()
+        k = V.shape[0]
+        Ad = _c128(A_data).reshape(-1, k)
+        Am = _c128(A_mc).reshape(-1, k)
+        wm = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+        ng = float(n_gen) if n_gen is not None else 0.0
+        nll = np.zeros(1)
+        grad = np.zeros(2 * k)
+        pr = np.zeros(2 + 4 * k)
+        if self.lib.orc_nll_grad_chunked(Ad.shape[0], _ptr(Ad), k, Am.shape[0], _ptr(Am), k, _ptr(wm), ng, k,
+                                         _ptr(V), int(bool(extended)), int(threads), _ptr(nll), _ptr(grad),
+                                         _ptr(pr)):
             raise ValueError("oracle: invalid arguments")
         if parts:
             d = dict(sum_log=pr[0], s_raw=pr[1], GD=pr[2:2 + 2 * k].copy(), HM=pr[2 + 2 * k:].copy())
@@ -146,6 +173,11 @@ def intensity(A, V):
 
 def nll_grad(A_data, A_mc, V, w=None, n_gen=None, extended=False, parts=False):
     return default().nll_grad(A_data, A_mc, V, w=w, n_gen=n_gen, extended=extended, parts=parts)
+
+
+def nll_grad_chunked(A_data, A_mc, V, w=None, n_gen=None, extended=False, threads=0, parts=False):
+    return default().nll_grad_chunked(A_data, A_mc, V, w=w, n_gen=n_gen, extended=extended, threads=threads,
+                                      parts=parts)
 
 
 def gram(A_mc, w=None, n_gen=None):

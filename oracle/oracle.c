@@ -25,7 +25,10 @@
  *
  * Arithmetic: plain double loops; every sum over events is a Neumaier
  * (compensated) sum in event order (the paper stresses that the final sum is
- * in double precision and that the summation algorithm matters).
+ * in double precision and that the summation algorithm matters).  The
+ * chunked form (orc_nll_grad_chunked) cuts the events into fixed chunks,
+ * sums each chunk in event order and adds the chunk sums in chunk order, so
+ * its result does not depend on how many threads run the chunks.
  *
  * Layout: complex arrays are interleaved (re, im) doubles; an event row holds
  * k complex values starting at row * ld complex (ld >= k).
@@ -38,6 +41,13 @@
 #include <stddef.h>
 #include <stdint.h>
 #include <stdlib.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+static int omp_default_threads(void) { return omp_get_max_threads(); }
+#else
+static int omp_default_threads(void) { return 1; }
+#endif
 
 typedef struct { double s, c; } nsum;   /* Neumaier accumulator */
 
@@ -213,6 +223,69 @@ int orc_nll_grad_gram(int64_t nd, const double *Ad, int64_t ldd, int32_t k, cons
     (void)Si;   /* zero up to rounding: M is Hermitian */
     /* With N_gen = 1 the raw MC quantities are S and M V themselves. */
     combine(nd, 1.0, k, extended, sum_log, GD, Sr, MV, bad, nll, grad);
+    free(GD);
+    return 0;
+}
+
+/* Rows per chunk of the chunked form. */
+#define ORC_CHUNK 65536
+
+/* Raw sums of one sample in chunks: chunk c holds rows [c ORC_CHUNK,
+ * (c + 1) ORC_CHUNK); each chunk's sums are raw_sums in row order, and the
+ * chunk sums are added in chunk order with Neumaier sums.  The chunks run on
+ * up to nthreads OpenMP threads; the order of every addition is fixed by the
+ * chunk layout alone.  Returns 1 if some data intensity is bad (as raw_sums). */
+static int raw_sums_chunked(int64_t n, int32_t k, const double *A, int64_t ld, const double *w,
+                            const double *V, int log_term, int nthreads, double *T, double *G) {
+    const int64_t nch = (n + ORC_CHUNK - 1) / ORC_CHUNK;
+    double *ct = (double *)calloc((size_t)(nch > 0 ? nch : 1), sizeof(double));
+    double *cg = (double *)calloc((size_t)(nch > 0 ? nch : 1) * (size_t)(2 * k), sizeof(double));
+    int *cb = (int *)calloc((size_t)(nch > 0 ? nch : 1), sizeof(int));
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+    for (int64_t c = 0; c < nch; ++c) {
+        const int64_t r0 = c * ORC_CHUNK;
+        const int64_t m = n - r0 < ORC_CHUNK ? n - r0 : ORC_CHUNK;
+        cb[c] = raw_sums(m, k, A + 2 * ld * r0, ld, w ? w + r0 : NULL, V, log_term, &ct[c], &cg[c * 2 * k]);
+    }
+    nsum t = {0.0, 0.0};
+    nsum *g = (nsum *)calloc((size_t)(2 * k), sizeof(nsum));
+    int bad = 0;
+    for (int64_t c = 0; c < nch; ++c) {
+        nadd(&t, ct[c]);
+        for (int32_t a = 0; a < 2 * k; ++a) nadd(&g[a], cg[c * 2 * k + a]);
+        bad |= cb[c];
+    }
+    *T = nval(&t);
+    for (int32_t a = 0; a < 2 * k; ++a) G[a] = nval(&g[a]);
+    free(g);
+    free(cb);
+    free(cg);
+    free(ct);
+    return bad;
+}
+
+/* orc_nll_grad on up to nthreads threads (<= 0: the OpenMP default) with the
+ * chunked sums above.  Same arguments and outputs as orc_nll_grad. */
+int orc_nll_grad_chunked(int64_t nd, const double *Ad, int64_t ldd,
+                         int64_t nm, const double *Am, int64_t ldm, const double *w, double n_gen,
+                         int32_t k, const double *V, int extended, int nthreads,
+                         double *nll, double *grad, double *parts) {
+    if (k < 1 || nd < 0 || nm < 0 || ldd < k || ldm < k || !V || !nll) return -1;
+    if ((nd > 0 && !Ad) || (nm > 0 && !Am)) return -1;
+    if (nd > 0 && nm == 0) return -1;
+    if (n_gen <= 0.0) n_gen = nm > 0 ? (double)nm : 1.0;
+    if (nthreads <= 0) nthreads = omp_default_threads();
+    double *GD = (double *)calloc((size_t)(4 * k), sizeof(double));
+    double *HM = GD + 2 * k;
+    double sum_log = 0.0, s_raw = 0.0;
+    int bad = raw_sums_chunked(nd, k, Ad, ldd, NULL, V, 1, nthreads, &sum_log, GD);
+    raw_sums_chunked(nm, k, Am, ldm, w, V, 0, nthreads, &s_raw, HM);
+    combine(nd, n_gen, k, extended, sum_log, GD, s_raw, HM, bad, nll, grad);
+    if (parts) {
+        parts[0] = sum_log;
+        parts[1] = s_raw;
+        for (int32_t a = 0; a < 2 * k; ++a) { parts[2 + a] = GD[a]; parts[2 + 2 * k + a] = HM[a]; }
+    }
     free(GD);
     return 0;
 }
