@@ -67,7 +67,9 @@ typedef enum {
 typedef enum { PWA_F32 = 0, PWA_F64 = 1 } pwa_prec;
 typedef enum { PWA_DATA = 0, PWA_MC = 1 } pwa_set;
 typedef enum { PWA_MC_STREAM = 0, PWA_MC_GRAM = 1 } pwa_mc_mode;
-typedef enum { PWA_HOST = 0, PWA_DEVICE = 1 } pwa_where;
+/* Where an array lives: host memory, device memory (copied), or device
+ * memory the library uses in place without a copy (pwa_set_amplitudes). */
+typedef enum { PWA_HOST = 0, PWA_DEVICE = 1, PWA_BORROW = 2 } pwa_where;
 
 /* Largest number of waves a context accepts. */
 #define PWA_MAX_K 64
@@ -84,9 +86,18 @@ pwa_status pwa_destroy(pwa_ctx *ctx);
 
 /* Store one sample (data or MC; Eq. 2's two sums).
  *   A      n x k complex in the context's precision, row stride ld complex,
- *          on the host or the device as `where` says.  The library copies it
- *          into its own padded device layout; the caller may free A when the
- *          call returns.
+ *          on the host or the device as `where` says.
+ *          PWA_HOST, PWA_DEVICE: the library copies A into its own padded
+ *          device layout; the caller may free A when the call returns.
+ *          PWA_BORROW: A (and w) are device memory of the context's device
+ *          that the library reads in place with no copy and no allocation of
+ *          sample memory.  A must already have the device layout: ld equal to
+ *          pwa_layout_ld() for k, a 16-byte aligned base, and zeros in columns
+ *          k..ld-1 of every row (checked with one pass over those columns).
+ *          The arrays must stay valid and unchanged until the sample is
+ *          replaced or the context destroyed; the library never frees them.
+ *          PWA_DEVICE and PWA_BORROW pointers that are not device memory of
+ *          the context's device are rejected with PWA_E_INVAL.
  *   n      number of events (0 allowed)
  *   k      number of waves, 1..PWA_MAX_K; data and MC must agree
  *   w      MC only: n per-event weights in the context's precision, in the
@@ -114,7 +125,9 @@ pwa_status pwa_set_mc_mode(pwa_ctx *ctx, pwa_mc_mode mode, int extended);
  * and gives NLL = 0 in the Eq. 2 form), PWA_E_DOMAIN, PWA_E_HIP. */
 pwa_status pwa_nll(pwa_ctx *ctx, const double *V, double *nll);
 
-/* NLL and gradient (host, 2k doubles) at V.  One fused pass over the rows.
+/* NLL and gradient (host, 2k doubles) at V.  One launch: a fused pass over
+ * the rows that ends with the fixed-order combine of its block partials and
+ * writes the result to mapped host memory, which the call polls.
  * Errors as pwa_nll. */
 pwa_status pwa_nll_grad(pwa_ctx *ctx, const double *V, double *nll, double *grad);
 
@@ -124,7 +137,8 @@ pwa_status pwa_nll_grad(pwa_ctx *ctx, const double *V, double *nll, double *grad
  *            [0] NLL (+inf on a domain failure), [1 .. 2k] gradient,
  *            [2k + 1] status flags (0 = ok, nonzero = PWA_E_DOMAIN)
  * Enqueues on the context's stream and returns; no wait, no allocation.
- * Errors (detected on the host only): PWA_E_INVAL, PWA_E_STATE, PWA_E_HIP. */
+ * Errors (detected on the host only): PWA_E_INVAL (also for pointers that are
+ * not device memory of the context's device), PWA_E_STATE, PWA_E_HIP. */
 pwa_status pwa_nll_grad_async(pwa_ctx *ctx, const double *V_dev, double *out_dev);
 
 /* NLL (and optionally gradients) for nv production vectors in one pass over
@@ -170,7 +184,8 @@ pwa_status pwa_nll_batch(pwa_ctx *ctx, int32_t nv, const double *V, double *nll,
  * synchronous pwa_nll_batch call with at least nv vectors and the same split
  * on the current samples creates; without them the call returns PWA_E_STATE
  * and enqueues nothing.  V_dev and out_dev must not overlap.
- * Errors (detected on the host only): PWA_E_INVAL, PWA_E_STATE,
+ * Errors (detected on the host only): PWA_E_INVAL (also for pointers that are
+ * not device memory of the context's device), PWA_E_STATE,
  * PWA_E_UNSUPPORTED, PWA_E_HIP. */
 pwa_status pwa_nll_batch_async(pwa_ctx *ctx, int32_t nv, const double *V_dev, double *out_dev,
                                int32_t split);
@@ -244,10 +259,10 @@ pwa_status pwa_set_stream_cfg(pwa_ctx *ctx, const pwa_stream_cfg *cfg);
 pwa_status pwa_autotune(pwa_ctx *ctx, int32_t reps, pwa_stream_cfg *best, double *best_ms);
 
 /* Kernel timing: average duration in ms of the streaming kernel (the pass over
- * the rows, without the small combine kernel that follows it) over the
+ * the rows and the combine of its block partials, one launch) over the
  * single-V evaluations since the last query, measured with HIP events on the
  * context's stream while timing is enabled with pwa_set_timing(ctx, 1).
- * Timing adds an event pair per call. */
+ * Timing records an event pair per call (events are reused). */
 pwa_status pwa_set_timing(pwa_ctx *ctx, int enable);
 pwa_status pwa_kernel_time(pwa_ctx *ctx, double *avg_ms, int64_t *count);
 

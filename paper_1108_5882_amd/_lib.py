@@ -19,7 +19,7 @@ OK, E_INVAL, E_NOMEM, E_HIP, E_DOMAIN, E_STATE, E_UNSUPPORTED = range(7)
 F32, F64 = 0, 1
 DATA, MC = 0, 1
 MC_STREAM, MC_GRAM = 0, 1
-HOST, DEVICE = 0, 1
+HOST, DEVICE, BORROW = 0, 1, 2
 MAX_K = 64
 
 # every entry point declared in include/pwa.h
@@ -176,10 +176,13 @@ class Context:
 
     def __init__(self, device: int = 0, precision: str = "f32", stream=None):
         self.lib = load()
+        self.device = int(device)
         self.prec = {"f32": F32, "f64": F64}[precision]
         self.real = np.float32 if self.prec == F32 else np.float64
         self.cplx = np.complex64 if self.prec == F32 else np.complex128
         self._stream_obj = stream          # keep a torch stream alive
+        self._borrowed = {}                # sample -> tensors the library reads in place
+        self._vbuf = self._obuf = None     # host V and result buffers of the synchronous calls
         h = ctypes.c_void_p()
         s = _stream_handle(stream)
         self._check(self.lib.pwa_create(ctypes.byref(h), device, self.prec,
@@ -200,6 +203,7 @@ class Context:
         if getattr(self, "h", None) is not None and self.h.value:
             self.lib.pwa_destroy(self.h)
             self.h = ctypes.c_void_p()
+        self._borrowed = {}
 
     def __del__(self):
         try:
@@ -214,27 +218,63 @@ class Context:
         self.close()
 
     # ------------------------------------------------------------ samples
-    def set_amplitudes(self, which: str, A, w=None, n_gen: Optional[float] = None):
-        """which: "data" or "mc".  A: numpy [n, k] complex (host) or a torch cuda
-        tensor [n, k] complex (device); w: matching weights or None."""
+    def _check_device_tensor(self, t, name: str, dtype):
+        """t must be a tensor on this context's GPU with the given torch dtype."""
+        if not _is_torch(t) or not t.is_cuda:
+            raise TypeError(f"{name} must be a torch tensor on a GPU")
+        if t.device.index != self.device:
+            raise ValueError(f"{name} is on cuda:{t.device.index}, the context on cuda:{self.device}")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+
+    def set_amplitudes(self, which: str, A, w=None, n_gen: Optional[float] = None, borrow: bool = False,
+                       k: Optional[int] = None):
+        """which: "data" or "mc".  A: numpy [n, k] complex (host) or a torch
+        tensor [n, k] complex (a CPU tensor is read as host memory, a GPU tensor
+        must be on the context's device); w: matching weights or None.
+
+        borrow=True: A (a GPU tensor [n, layout_ld(k)] with zero padding
+        columns; k defaults to its width) and w are used in place with no
+        copy; the context keeps references to them until the sample is
+        replaced or the context closed."""
         wh = {"data": DATA, "mc": MC}[which]
+        if _is_torch(A) and not A.is_cuda:
+            if borrow:
+                raise TypeError("only a GPU tensor can be borrowed")
+            A = A.numpy()
+            w = None if w is None else (w.numpy() if _is_torch(w) else w)
         if _is_torch(A):
+            import torch
+            self._check_device_tensor(A, "A", {F32: torch.complex64, F64: torch.complex128}[self.prec])
             if A.dim() != 2:
                 raise ValueError("A must be [n, k]")
-            n, k = A.shape
+            n = A.shape[0]
+            k = A.shape[1] if k is None else int(k)
+            if not 1 <= k <= A.shape[1]:
+                raise ValueError("k must be between 1 and the width of A")
             ld = A.stride(0)
             if A.stride(1) != 1:
                 raise ValueError("A must have unit stride along k")
-            if A.dtype != {F32: __import__("torch").complex64, F64: __import__("torch").complex128}[self.prec]:
-                raise TypeError("A dtype does not match the context precision")
+            if borrow:
+                ld_dev = self.layout_ld(k)
+                if n > 1 and ld != ld_dev:
+                    raise ValueError(f"a borrowed A needs row stride {ld_dev} for k = {k}, got {ld}")
+                ld = ld_dev
             wp = None
             if w is not None:
+                self._check_device_tensor(w, "w", {F32: torch.float32, F64: torch.float64}[self.prec])
                 if not w.is_contiguous() or w.numel() != n:
                     raise ValueError("w must be contiguous [n]")
                 wp = ctypes.c_void_p(w.data_ptr())
             self._check(self.lib.pwa_set_amplitudes(self.h, wh, ctypes.c_void_p(A.data_ptr()), n, k, ld,
-                                                    DEVICE, wp, float(n_gen or 0.0)))
+                                                    BORROW if borrow else DEVICE, wp, float(n_gen or 0.0)))
+            if borrow:
+                self._borrowed[which] = (A, w)
+            else:
+                self._borrowed.pop(which, None)
         else:
+            if borrow:
+                raise TypeError("only a GPU tensor can be borrowed")
             A = np.ascontiguousarray(A, dtype=self.cplx)
             if A.ndim != 2:
                 raise ValueError("A must be [n, k]")
@@ -244,6 +284,9 @@ class Context:
                 raise ValueError("w must be [n]")
             self._check(self.lib.pwa_set_amplitudes(self.h, wh, _ptr(A), n, k, k, HOST, _ptr(wa),
                                                     float(n_gen or 0.0)))
+            self._borrowed.pop(which, None)
+        if self.k != k:
+            self._borrowed = {which: self._borrowed[which]} if which in self._borrowed else {}
         self.k = k
 
     def set_mc_mode(self, mode: str = "stream", extended: bool = False):
@@ -259,22 +302,46 @@ class Context:
             return out
         return np.ascontiguousarray(V, dtype=np.float64)
 
+    def _stage_v(self, V):
+        """Copies V ([k] complex or [2k] real) into the context's host buffer;
+        returns (address of V, address of the result buffer [nll, grad[2k]])."""
+        if self.k is None:
+            raise PwaError(E_STATE, "no sample set")
+        n = 2 * self.k
+        if self._vbuf is None or self._vbuf.size != n:
+            self._vbuf = np.zeros(n)
+            self._obuf = np.zeros(n + 1)
+            self._vptr = self._vbuf.ctypes.data
+            self._optr = self._obuf.ctypes.data
+        if isinstance(V, np.ndarray) and V.dtype == np.complex128 and V.ndim == 1 and V.flags.c_contiguous:
+            v = V.view(np.float64)
+        else:
+            v = self._v(V).ravel()
+        if v.size != n:
+            raise ValueError(f"V must hold {self.k} complex (or {n} real) values, got {v.size} reals")
+        self._vbuf[:] = v
+        return self._vptr, self._optr
+
     def nll(self, V) -> float:
-        v = self._v(V)
-        out = np.zeros(1)
-        self._check(self.lib.pwa_nll(self.h, _ptr(v), _ptr(out)))
-        return float(out[0])
+        vp, op = self._stage_v(V)
+        self._check(self.lib.pwa_nll(self.h, vp, op))
+        return float(self._obuf[0])
 
     def nll_grad(self, V):
         """(NLL, gradient[2k]) with gradient = (dNLL/dRe V_a, dNLL/dIm V_a) interleaved."""
-        v = self._v(V)
-        out = np.zeros(1)
-        g = np.zeros(v.size)
-        self._check(self.lib.pwa_nll_grad(self.h, _ptr(v), _ptr(out), _ptr(g)))
-        return float(out[0]), g
+        vp, op = self._stage_v(V)
+        self._check(self.lib.pwa_nll_grad(self.h, vp, op, op + 8))
+        return float(self._obuf[0]), self._obuf[1:].copy()
 
     def nll_grad_async(self, V_dev, out_dev):
-        """V_dev: torch cuda float64 [2k]; out_dev: torch cuda float64 [2k+2]."""
+        """V_dev: torch float64 [2k] on the context's GPU; out_dev: the same, [2k+2]."""
+        import torch
+        self._check_device_tensor(V_dev, "V_dev", torch.float64)
+        self._check_device_tensor(out_dev, "out_dev", torch.float64)
+        if self.k is None or V_dev.numel() != 2 * self.k or out_dev.numel() != 2 * self.k + 2:
+            raise ValueError("V_dev must hold 2k and out_dev 2k + 2 doubles")
+        if not (V_dev.is_contiguous() and out_dev.is_contiguous()):
+            raise ValueError("V_dev and out_dev must be contiguous")
         self._check(self.lib.pwa_nll_grad_async(self.h, ctypes.c_void_p(V_dev.data_ptr()),
                                                 ctypes.c_void_p(out_dev.data_ptr())))
 
@@ -312,6 +379,11 @@ class Context:
         [nv, 2k + 2] contiguous (per vector: nll, grad[2k], flags).  Enqueued on
         the context's stream; a synchronous nll_batch with at least nv vectors and
         the same split must have prepared the workspace."""
+        import torch
+        self._check_device_tensor(V_dev, "V_dev", torch.float64)
+        self._check_device_tensor(out_dev, "out_dev", torch.float64)
+        if V_dev.dim() != 2 or out_dev.dim() != 2:
+            raise ValueError("V_dev must be [nv, 2k] and out_dev [nv, 2k + 2]")
         nv = V_dev.shape[0]
         if not (V_dev.is_contiguous() and out_dev.is_contiguous()):
             raise ValueError("V_dev and out_dev must be contiguous")

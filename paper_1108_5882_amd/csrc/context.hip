@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -23,6 +24,7 @@ namespace {
 struct Sample {
     void *A = nullptr;       // device rows, ld complex each
     void *w = nullptr;       // device weights (MC) or null
+    bool owned = true;       // false: the caller's arrays, used in place (PWA_BORROW)
     int64_t n = 0;
     double n_gen = 0.0;
     bool set = false;
@@ -62,16 +64,21 @@ struct pwa_ctx {
     double *gram = nullptr;          // k x k complex FP64 (1/N_gen folded)
     bool gram_valid = false;
 
-    double *partials = nullptr;
-    size_t partials_doubles = 0;
+    double *partials = nullptr;      // block partials, then group sums (stream_scratch_doubles)
+    double *gsums = nullptr;
+    unsigned *counters = nullptr;    // arrival counters of the in-kernel combine (zero between launches)
     double *out_dev = nullptr;       // [nll, grad[2k], flags]
-    double *out_host = nullptr;      // mapped pinned host memory the combine writes to
+    double *out_host = nullptr;      // mapped pinned host memory the kernel writes the result to
     double *out_host_dev = nullptr;  // device address of out_host
+    unsigned long long *done_host = nullptr;   // sequence word after the result (mapped)
+    unsigned long long *done_dev = nullptr;
+    unsigned long long seq = 0;
     uint32_t last_flags = 0;
 
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> batch_events;
+    std::vector<hipEvent_t> event_pool;   // timing events kept for reuse
 
     // batched (many-V) path: per-wave FP16 scales of the amplitudes, device scratch
     bool amax_valid = false;
@@ -134,34 +141,30 @@ pwa_status hip_fail(pwa_ctx *ctx, hipError_t e, const char *what) {
 
 size_t elem_bytes(pwa_prec p) { return p == PWA_F32 ? sizeof(float) : sizeof(double); }
 
+// PWA_OK if p is device memory of the context's device (or managed memory).
+pwa_status check_device_ptr(pwa_ctx *ctx, const void *p, const char *what) {
+    hipPointerAttribute_t at;
+    std::memset(&at, 0, sizeof at);
+    const hipError_t e = hipPointerGetAttributes(&at, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();   // clear the error this query leaves behind
+        return fail(ctx, PWA_E_INVAL, "%s is not device memory", what);
+    }
+    if (!(at.type == hipMemoryTypeDevice || at.isManaged))
+        return fail(ctx, PWA_E_INVAL, "%s is not device memory", what);
+    if (!at.isManaged && at.device != ctx->device)
+        return fail(ctx, PWA_E_INVAL, "%s is on device %d, the context on device %d", what, at.device, ctx->device);
+    return PWA_OK;
+}
+
 void free_sample(Sample &s) {
-    if (s.A) (void)hipFree(s.A);
-    if (s.w) (void)hipFree(s.w);
+    if (s.owned && s.A) (void)hipFree(s.A);
+    if (s.owned && s.w) (void)hipFree(s.w);
     s = Sample{};
 }
 
-// Grid for one evaluation: blocks per segment, at most what the rows need and
-// at most blocks_per_cu per compute unit overall, split in proportion to rows.
 void split_blocks(const pwa_ctx *ctx, int64_t n0, int64_t n1, int32_t nb[2]) {
-    const int rows_per_wave = stream_rows_per_wave(ctx->cfg);
-    const int waves_per_block = kStreamThreads / 64;
-    const int64_t rows_per_block = (int64_t)rows_per_wave * waves_per_block;
-    int64_t need[2] = {(n0 + rows_per_block - 1) / rows_per_block,
-                       (n1 + rows_per_block - 1) / rows_per_block};
-    const int64_t budget = (int64_t)ctx->cu_count * ctx->cfg.blocks_per_cu;
-    if (need[0] + need[1] <= budget) {
-        nb[0] = (int32_t)need[0];
-        nb[1] = (int32_t)need[1];
-        return;
-    }
-    const double frac = (double)n0 / (double)(n0 + n1);
-    int64_t b0 = (int64_t)std::llround(frac * (double)budget);
-    if (n0 > 0) b0 = std::max<int64_t>(b0, 1);
-    if (n1 > 0) b0 = std::min<int64_t>(b0, budget - 1);
-    b0 = std::min(b0, need[0]);
-    int64_t b1 = std::min(budget - b0, need[1]);
-    nb[0] = (int32_t)b0;
-    nb[1] = (int32_t)b1;
+    stream_grid(ctx->cfg, (int64_t)ctx->cu_count * ctx->cfg.blocks_per_cu, n0, n1, nb);
 }
 
 pwa_status ensure_gram(pwa_ctx *ctx) {
@@ -211,6 +214,8 @@ pwa_status prepare(pwa_ctx *ctx, StreamArgs &a, int *blocks) {
     a.k = ctx->k;
     a.pstride = (int32_t)(1 + 2 * ctx->ld);
     a.partials = ctx->partials;
+    a.gsums = ctx->gsums;
+    a.counters = ctx->counters;
     a.gram = gram && need_mc ? ctx->gram : nullptr;
     a.n_gen = ctx->s[1].n_gen > 0 ? ctx->s[1].n_gen : 1.0;
     a.nd_total = (double)nd;
@@ -220,21 +225,53 @@ pwa_status prepare(pwa_ctx *ctx, StreamArgs &a, int *blocks) {
     return PWA_OK;
 }
 
+// A timing event from the context's pool (created when the pool is empty).
+pwa_status take_event(pwa_ctx *ctx, hipEvent_t *ev) {
+    if (!ctx->event_pool.empty()) {
+        *ev = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+        return PWA_OK;
+    }
+    PWA_HIP(ctx, hipEventCreate(ev), "hipEventCreate");
+    return PWA_OK;
+}
+
 pwa_status launch(pwa_ctx *ctx, const StreamArgs &a, int blocks) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    pwa_status st;
     if (ctx->timing) {
-        PWA_HIP(ctx, hipEventCreate(&e0), "hipEventCreate");
-        PWA_HIP(ctx, hipEventCreate(&e1), "hipEventCreate");
+        if ((st = take_event(ctx, &e0)) != PWA_OK) return st;
+        if ((st = take_event(ctx, &e1)) != PWA_OK) {
+            ctx->event_pool.push_back(e0);
+            return st;
+        }
+        ctx->events.emplace_back(e0, e1);
         PWA_HIP(ctx, hipEventRecord(e0, ctx->stream), "hipEventRecord");
     }
     hipError_t e = launch_stream(ctx->prec, ctx->cfg, blocks, a, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "likelihood kernel launch");
-    if (ctx->timing) {
-        PWA_HIP(ctx, hipEventRecord(e1, ctx->stream), "hipEventRecord");
-        ctx->events.emplace_back(e0, e1);
+    if (ctx->timing) PWA_HIP(ctx, hipEventRecord(e1, ctx->stream), "hipEventRecord");
+    return PWA_OK;
+}
+
+// Waits until the kernel has written the result of the launch numbered seq to
+// host memory: polls the mapped sequence word, asking the stream for errors
+// every few thousand polls (a failed or finished stream ends the wait).
+pwa_status wait_result(pwa_ctx *ctx, unsigned long long seq) {
+    const volatile unsigned long long *done = ctx->done_host;
+    for (unsigned spin = 1;; ++spin) {
+        if (*done == seq) break;
+        if ((spin & 4095u) == 0) {
+            const hipError_t q = hipStreamQuery(ctx->stream);
+            if (q == hipSuccess) {
+                if (*done == seq) break;
+                return fail(ctx, PWA_E_HIP, "likelihood kernel finished without writing its result");
+            }
+            if (q != hipErrorNotReady) return hip_fail(ctx, q, "likelihood kernel");
+        }
+        __builtin_ia32_pause();
     }
-    e = launch_combine(a, stream_log_scale(ctx->prec), ctx->stream);
-    if (e != hipSuccess) return hip_fail(ctx, e, "combine kernel launch");
+    std::atomic_thread_fence(std::memory_order_acquire);
     return PWA_OK;
 }
 
@@ -261,8 +298,11 @@ pwa_status eval_sync(pwa_ctx *ctx, const double *V, double *nll, double *grad) {
     if (blocks == 0 && !a.gram) {
         trivial_result(ctx, res);
     } else {
-        // the combine kernel writes the result straight into mapped host memory
+        // the kernel writes the result straight into mapped host memory, then
+        // the call's sequence number after it
         a.out = ctx->out_host_dev;
+        a.done = ctx->done_dev;
+        a.seq = ++ctx->seq;
         if (blocks == 0) {
             // Gram form with no data rows: one block runs the combine alone
             a.nb[0] = 1;
@@ -270,7 +310,7 @@ pwa_status eval_sync(pwa_ctx *ctx, const double *V, double *nll, double *grad) {
         }
         st = launch(ctx, a, blocks);
         if (st != PWA_OK) return st;
-        PWA_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        if ((st = wait_result(ctx, a.seq)) != PWA_OK) return st;
     }
     ctx->last_flags = (uint32_t)res[2 * k + 1];
     *nll = res[0];
@@ -445,18 +485,19 @@ pwa_status batch_launch(pwa_ctx *ctx, int32_t nv, const double *V_dev, double *o
     if (e != hipSuccess) return hip_fail(ctx, e, "batched weights launch");
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (ctx->timing && alloc) {
-        PWA_HIP(ctx, hipEventCreate(&e0), "hipEventCreate");
-        PWA_HIP(ctx, hipEventCreate(&e1), "hipEventCreate");
+        if ((st = take_event(ctx, &e0)) != PWA_OK) return st;
+        if ((st = take_event(ctx, &e1)) != PWA_OK) {
+            ctx->event_pool.push_back(e0);
+            return st;
+        }
+        ctx->batch_events.emplace_back(e0, e1);
         PWA_HIP(ctx, hipEventRecord(e0, ctx->stream), "hipEventRecord");
     }
     e = launch_batch(a, refine, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "batched kernel launch");
     if (refine && (e = launch_batch_refine(a, ctx->stream)) != hipSuccess)
         return hip_fail(ctx, e, "refinement launch");
-    if (e0) {
-        PWA_HIP(ctx, hipEventRecord(e1, ctx->stream), "hipEventRecord");
-        ctx->batch_events.emplace_back(e0, e1);
-    }
+    if (e0) PWA_HIP(ctx, hipEventRecord(e1, ctx->stream), "hipEventRecord");
     e = launch_batch_combine(a, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "batched combine launch");
     return PWA_OK;
@@ -493,6 +534,16 @@ pwa_status batch_mfma(pwa_ctx *ctx, int32_t nv, const double *V, double *nll, do
 }  // namespace
 
 namespace pwa {
+
+void set_global_error(const char *msg) { g_err = msg; }
+
+bool stream_tuned_cfg(int device, pwa_prec prec, int64_t ld, int64_t nd, int64_t nm, StreamCfg *cfg) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(TuneKey{device, (int)prec, ld, nd, nm});
+    if (it == g_tune_cache.end()) return false;
+    *cfg = it->second;
+    return true;
+}
 
 hipError_t stage_rows(void *dst, size_t dst_pitch, const void *src, size_t src_pitch, size_t width, size_t n,
                       hipMemcpyKind kind, hipStream_t stream) {
@@ -634,20 +685,28 @@ pwa_status pwa_create(pwa_ctx **out, int device, pwa_prec prec, void *stream) {
         }
         ctx->own_stream = true;
     }
-    const size_t max_blocks = (size_t)ctx->cu_count * kMaxBlocksPerCu;
-    ctx->partials_doubles = max_blocks * (1 + 2 * PWA_MAX_K);
-    const size_t out_bytes = sizeof(double) * (2 * PWA_MAX_K + 2);
-    if ((e = hipMalloc(&ctx->partials, sizeof(double) * ctx->partials_doubles)) != hipSuccess ||
-        (e = hipMalloc(&ctx->out_dev, out_bytes)) != hipSuccess ||
-        (e = hipHostMalloc(&ctx->out_host, out_bytes, hipHostMallocMapped | hipHostMallocCoherent)) !=
+    const int max_blocks = ctx->cu_count * kMaxBlocksPerCu;
+    const int max_ps = 1 + 2 * PWA_MAX_K;
+    const size_t out_doubles = 2 * PWA_MAX_K + 2;
+    const size_t cwords = stream_counter_words(max_blocks);
+    if ((e = hipMalloc(&ctx->partials, sizeof(double) * stream_scratch_doubles(max_blocks, max_ps))) !=
             hipSuccess ||
+        (e = hipMalloc(&ctx->counters, sizeof(unsigned) * cwords)) != hipSuccess ||
+        (e = hipMemsetAsync(ctx->counters, 0, sizeof(unsigned) * cwords, ctx->stream)) != hipSuccess ||
+        (e = hipMalloc(&ctx->out_dev, sizeof(double) * out_doubles)) != hipSuccess ||
+        (e = hipHostMalloc(&ctx->out_host, sizeof(double) * (out_doubles + 1),
+                           hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess ||
         (e = hipHostGetDevicePointer((void **)&ctx->out_host_dev, ctx->out_host, 0)) != hipSuccess ||
-        (e = hipDeviceSynchronize()) != hipSuccess) {
+        (e = hipStreamSynchronize(ctx->stream)) != hipSuccess) {
         pwa_status st = e == hipErrorOutOfMemory ? PWA_E_NOMEM : PWA_E_HIP;
         fail(nullptr, st, "context allocation: %s", hipGetErrorString(e));
         pwa_destroy(ctx);
         return st;
     }
+    ctx->gsums = ctx->partials + (size_t)max_blocks * max_ps;
+    ctx->done_host = reinterpret_cast<unsigned long long *>(ctx->out_host + out_doubles);
+    ctx->done_dev = reinterpret_cast<unsigned long long *>(ctx->out_host_dev + out_doubles);
+    *ctx->done_host = 0;
     *out = ctx;
     return PWA_OK;
 }
@@ -662,6 +721,8 @@ pwa_status pwa_destroy(pwa_ctx *ctx) {
             (void)hipEventDestroy(ev.first);
             (void)hipEventDestroy(ev.second);
         }
+    for (hipEvent_t ev : ctx->event_pool) (void)hipEventDestroy(ev);
+    if (ctx->counters) (void)hipFree(ctx->counters);
     if (ctx->gram) (void)hipFree(ctx->gram);
     for (void *b : {ctx->b_wfrag, ctx->b_ascale, ctx->b_vscale, ctx->b_V, ctx->b_partials, ctx->b_out,
                     (void *)ctx->b_amax, (void *)ctx->b_rnorm, ctx->b_flags, ctx->h_buf})
@@ -678,7 +739,8 @@ pwa_status pwa_set_amplitudes(pwa_ctx *ctx, pwa_set which, const void *A, int64_
                               int64_t ld, pwa_where where, const void *w, double n_gen) {
     if (!ctx) return fail(nullptr, PWA_E_INVAL, "null context");
     if (which != PWA_DATA && which != PWA_MC) return fail(ctx, PWA_E_INVAL, "bad sample id");
-    if (where != PWA_HOST && where != PWA_DEVICE) return fail(ctx, PWA_E_INVAL, "bad memory space");
+    if (where != PWA_HOST && where != PWA_DEVICE && where != PWA_BORROW)
+        return fail(ctx, PWA_E_INVAL, "bad memory space");
     if (n < 0) return fail(ctx, PWA_E_INVAL, "negative n");
     if (k < 1) return fail(ctx, PWA_E_INVAL, "k must be >= 1");
     if (k > PWA_MAX_K) return fail(ctx, PWA_E_UNSUPPORTED, "k = %d exceeds %d", k, PWA_MAX_K);
@@ -686,6 +748,33 @@ pwa_status pwa_set_amplitudes(pwa_ctx *ctx, pwa_set which, const void *A, int64_
     if (n > 0 && !A) return fail(ctx, PWA_E_INVAL, "null A");
     if (which == PWA_DATA && w) return fail(ctx, PWA_E_INVAL, "weights apply to the MC sample only");
     DeviceGuard dg(ctx->device);
+    const size_t eb = elem_bytes(ctx->prec);
+    if (where != PWA_HOST && n > 0) {
+        pwa_status st;
+        if ((st = check_device_ptr(ctx, A, "A")) != PWA_OK) return st;
+        if (w && (st = check_device_ptr(ctx, w, "w")) != PWA_OK) return st;
+    }
+    if (where == PWA_BORROW) {
+        const int64_t lay = stream_layout_ld(ctx->prec, k);
+        if (ld != lay)
+            return fail(ctx, PWA_E_INVAL, "a borrowed sample needs the device layout: ld = %lld for k = %d",
+                        (long long)lay, k);
+        if (n > 0 && reinterpret_cast<uintptr_t>(A) % 16 != 0)
+            return fail(ctx, PWA_E_INVAL, "a borrowed A must be 16-byte aligned");
+        if (w && reinterpret_cast<uintptr_t>(w) % eb != 0)
+            return fail(ctx, PWA_E_INVAL, "borrowed weights must be aligned to their element size");
+        if (n > 0 && ld > k) {
+            unsigned *bad = nullptr, hbad = 0;
+            PWA_HIP(ctx, hipMalloc(&bad, sizeof(unsigned)), "hipMalloc(check)");
+            hipError_t e = hipMemsetAsync(bad, 0, sizeof(unsigned), ctx->stream);
+            if (e == hipSuccess) e = launch_pad_check(ctx->prec, A, n, ld, k, bad, ctx->stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof hbad, hipMemcpyDeviceToHost, ctx->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+            (void)hipFree(bad);
+            if (e != hipSuccess) return hip_fail(ctx, e, "padding check");
+            if (hbad) return fail(ctx, PWA_E_INVAL, "a borrowed A must hold zeros in columns k..ld-1");
+        }
+    }
 
     const int other = which == PWA_DATA ? 1 : 0;
     if (ctx->k != k) {
@@ -702,9 +791,12 @@ pwa_status pwa_set_amplitudes(pwa_ctx *ctx, pwa_set which, const void *A, int64_
     ctx->amax_valid = false;
     if (which == PWA_DATA) ctx->rnorm_valid = false;
 
-    const size_t eb = elem_bytes(ctx->prec);
     const size_t row_bytes = 2 * eb * (size_t)ctx->ld;
-    if (n > 0) {
+    if (where == PWA_BORROW) {
+        s.A = n > 0 ? const_cast<void *>(A) : nullptr;
+        s.w = n > 0 ? const_cast<void *>(w) : nullptr;
+        s.owned = false;
+    } else if (n > 0) {
         PWA_HIP(ctx, hipMalloc(&s.A, row_bytes * (size_t)n), "hipMalloc(amplitudes)");
         const hipMemcpyKind kind = where == PWA_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
         PWA_HIP(ctx, stage_rows(s.A, row_bytes, A, 2 * eb * (size_t)ld, 2 * eb * (size_t)k, (size_t)n, kind,
@@ -753,6 +845,10 @@ pwa_status pwa_nll_grad(pwa_ctx *ctx, const double *V, double *nll, double *grad
 pwa_status pwa_nll_grad_async(pwa_ctx *ctx, const double *V_dev, double *out_dev) {
     if (!ctx) return fail(nullptr, PWA_E_INVAL, "null context");
     if (!V_dev || !out_dev) return fail(ctx, PWA_E_INVAL, "null device pointer");
+    pwa_status pst;
+    if ((pst = check_device_ptr(ctx, V_dev, "V_dev")) != PWA_OK ||
+        (pst = check_device_ptr(ctx, out_dev, "out_dev")) != PWA_OK)
+        return pst;
     if (ctx->mode == PWA_MC_GRAM && !ctx->gram_valid)
         return fail(ctx, PWA_E_STATE, "MC matrix not built: run one synchronous evaluation first");
     DeviceGuard dg(ctx->device);
@@ -805,6 +901,10 @@ pwa_status pwa_nll_batch_async(pwa_ctx *ctx, int32_t nv, const double *V_dev, do
     if (split >= 2 && ctx->prec != PWA_F32)
         return fail(ctx, PWA_E_UNSUPPORTED, "the matrix-core path needs an FP32 context");
     if (nv == 0) return PWA_OK;
+    pwa_status pst;
+    if ((pst = check_device_ptr(ctx, V_dev, "V_dev")) != PWA_OK ||
+        (pst = check_device_ptr(ctx, out_dev, "out_dev")) != PWA_OK)
+        return pst;
     const int k = ctx->k;
     if (split == 0) {
         for (int32_t b = 0; b < nv; ++b) {
@@ -923,11 +1023,8 @@ pwa_status pwa_autotune(pwa_ctx *ctx, int32_t reps, pwa_stream_cfg *best, double
             split_blocks(ctx, a.n[0], a.n[1], a.nb);
             int nb = a.nb[0] + a.nb[1];
             if (nb < 1) { a.nb[0] = 1; nb = 1; }
-            // time the pass over the rows together with the combine it needs
-            auto both = [&]() {
-                hipError_t e2 = launch_stream(ctx->prec, ctx->cfg, nb, a, ctx->stream);
-                return e2 != hipSuccess ? e2 : launch_combine(a, stream_log_scale(ctx->prec), ctx->stream);
-            };
+            // the pass over the rows with the combine of its partials
+            auto both = [&]() { return launch_stream(ctx->prec, ctx->cfg, nb, a, ctx->stream); };
             if ((err = both()) != hipSuccess) break;
             if ((err = hipEventRecord(e0, ctx->stream)) != hipSuccess) break;
             for (int r = 0; r < reps && err == hipSuccess; ++r) err = both();
@@ -980,8 +1077,8 @@ pwa_status drain_events(pwa_ctx *ctx, std::vector<std::pair<hipEvent_t, hipEvent
         PWA_HIP(ctx, hipEventElapsedTime(&ms, ev.first, ev.second), "hipEventElapsedTime");
         total += ms;
         ++m;
-        (void)hipEventDestroy(ev.first);
-        (void)hipEventDestroy(ev.second);
+        ctx->event_pool.push_back(ev.first);
+        ctx->event_pool.push_back(ev.second);
     }
     list.clear();
     *avg_ms = m ? total / (double)m : 0.0;

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 
@@ -22,8 +23,12 @@ struct StreamArgs {
     int32_t k;                 // waves
     int32_t pstride;           // doubles per block partial (1 + 2 ld)
     const double *v_dev;       // V on the device (2k doubles) or nullptr
-    double *partials;          // [pstride][nb[0] + nb[1]] block partials (column-major)
+    double *partials;          // [nb[0] + nb[1]][pstride] block partials
+    double *gsums;             // [groups][2 pstride] sums of groups of kFinishGroup blocks
+    unsigned *counters;        // [1 + groups] arrival counts: zero before a launch and after it
     double *out;               // [nll, grad[2k], flags]
+    unsigned long long *done;  // or nullptr: receives seq once out is written (host-mapped memory)
+    unsigned long long seq;
     const double *gram;        // MC matrix (k x k complex FP64, 1/N_gen folded) or nullptr
     double n_gen;              // N_gen of the MC estimate (stream mode)
     double nd_total;           // N_D as a double
@@ -62,14 +67,33 @@ StreamCfg stream_default_cfg(pwa_prec prec, int ld);
 // True if (L, C, U) is compiled for the precision.
 bool stream_cfg_available(pwa_prec prec, const StreamCfg &c);
 
-// Adds the block partials in a fixed order and writes [nll, grad[2k], flags]
-// to args.out (one block).  log_scale converts the summed log term to ln.
-hipError_t launch_combine(const StreamArgs &args, double log_scale, hipStream_t stream);
+// Grid of one evaluation over n0 data and n1 MC rows: blocks per segment, at
+// most what the rows need and at most `budget` in all, split in proportion to
+// the rows.
+void stream_grid(const StreamCfg &cfg, int64_t budget, int64_t n0, int64_t n1, int32_t nb[2]);
 
-// Scale that turns the streaming kernel's summed log term into ln (log2 sums in FP32 contexts).
-double stream_log_scale(pwa_prec prec);
+// Message pwa_last_error(NULL) returns on this thread.
+void set_global_error(const char *msg);
 
-// Launches the streaming kernel (block partials only); returns hipSuccess or the launch error.
+// Configuration pwa_autotune chose for these sample sizes in this process, if any.
+bool stream_tuned_cfg(int device, pwa_prec prec, int64_t ld, int64_t nd, int64_t nm, StreamCfg *cfg);
+
+// The streaming kernel ends with the combine of its block partials: the last
+// block of each group of kFinishGroup consecutive blocks adds the group's
+// partials in block order, and the last group to finish adds the group sums
+// in group order and writes [nll, grad[2k], flags] to args.out (a fixed order
+// throughout, so results are bitwise reproducible for a launch configuration).
+constexpr int kFinishGroup = 16;
+inline int stream_groups(int blocks) { return (blocks + kFinishGroup - 1) / kFinishGroup; }
+// Doubles of block partials and group sums a launch of `blocks` blocks needs.
+inline size_t stream_scratch_doubles(int blocks, int pstride) {
+    return (size_t)blocks * pstride + (size_t)stream_groups(blocks) * 2 * pstride;
+}
+// Counters a launch of `blocks` blocks needs (zero before the first launch).
+inline size_t stream_counter_words(int blocks) { return 1 + (size_t)stream_groups(blocks); }
+
+// Launches the streaming kernel (the pass over the rows and the combine of its
+// block partials); returns hipSuccess or the launch error.
 hipError_t launch_stream(pwa_prec prec, const StreamCfg &cfg, int blocks, const StreamArgs &args,
                          hipStream_t stream);
 
@@ -192,6 +216,12 @@ hipError_t launch_lbfgs(const MultiFit *fits, int k_all, const double *out, int6
 // device.
 hipError_t stage_rows(void *dst, size_t dst_pitch, const void *src, size_t src_pitch, size_t width, size_t n,
                       hipMemcpyKind kind, hipStream_t stream);
+
+// Sets *bad (device word, zeroed by the caller) to 1 if a row of the sample
+// (n rows of ld complex in the precision) holds a nonzero value in columns
+// [k, ld).  Nothing is launched when ld == k.
+hipError_t launch_pad_check(pwa_prec prec, const void *A, int64_t n, int64_t ld, int k, unsigned *bad,
+                            hipStream_t stream);
 
 // Gram matrix of the MC rows (Eq. 3 bracket), FP64 result on the device.
 //   partials: device scratch of at least gram_partial_doubles(k, blocks) doubles.

@@ -1,4 +1,6 @@
 // Variant table, layout width and launch dispatch of the fused likelihood kernel.
+#include <algorithm>
+#include <cmath>
 #include <cstdlib>
 
 #include "internal.hpp"
@@ -85,7 +87,23 @@ StreamCfg stream_default_cfg(pwa_prec prec, int ld) {
     return best;
 }
 
-double stream_log_scale(pwa_prec prec) { return prec == PWA_F32 ? 0.69314718055994530942 : 1.0; }
+void stream_grid(const StreamCfg &cfg, int64_t budget, int64_t n0, int64_t n1, int32_t nb[2]) {
+    const int64_t rows_per_block = (int64_t)stream_rows_per_wave(cfg) * (kStreamThreads / 64);
+    const int64_t need[2] = {(n0 + rows_per_block - 1) / rows_per_block, (n1 + rows_per_block - 1) / rows_per_block};
+    if (need[0] + need[1] <= budget) {
+        nb[0] = (int32_t)need[0];
+        nb[1] = (int32_t)need[1];
+        return;
+    }
+    const double frac = (double)n0 / (double)(n0 + n1);
+    int64_t b0 = (int64_t)std::llround(frac * (double)budget);
+    if (n0 > 0) b0 = std::max<int64_t>(b0, 1);
+    if (n1 > 0) b0 = std::min<int64_t>(b0, budget - 1);
+    b0 = std::min(b0, need[0]);
+    const int64_t b1 = std::min(budget - b0, need[1]);
+    nb[0] = (int32_t)b0;
+    nb[1] = (int32_t)b1;
+}
 
 hipError_t launch_stream(pwa_prec prec, const StreamCfg &c, int blocks, const StreamArgs &args,
                          hipStream_t stream) {

@@ -5,10 +5,12 @@
 //                conj(A_ia) z_i / I_i                  (Eq. 2 data term and its derivative)
 //   MC row j:    accumulate w_j I_j and w_j conj(A_ja) z_j   (MC estimate of the
 //                normalisation integral and its derivative)
-// Each block writes one FP64 partial; a separate combine kernel adds the
-// partials in a fixed order and forms NLL and the real gradient.  The kernel
-// boundary orders the partial stores before the combine's loads, so no block
-// pays for a device-scope fence or atomic.
+// Each block writes one FP64 partial.  The same launch then combines them:
+// the last block to finish in each group of kFinishGroup consecutive blocks
+// (found with an arrival counter) adds its group's partials in block order,
+// and the last group to finish adds the group sums in group order and forms
+// NLL and the real gradient.  Every addition has a fixed place in that order,
+// so results are bitwise reproducible for a launch configuration.
 //
 // Layout and mapping (gfx950, 64-lane waves): an event row is ld = L*C complex
 // values; L consecutive lanes share a row and lane j holds complexes
@@ -145,6 +147,169 @@ struct EventMath<double> {
     static __device__ __forceinline__ double recip(double I) { return 1.0 / I; }
     static constexpr double kLogScale = 1.0;
 };
+
+// ------------------------------------------- combine of the block partials
+// Partials and group sums cross blocks, and so the XCDs' separate L2 caches.
+// They are stored and loaded as device-scope atomics (written through to, and
+// read from, the device's coherence point), and each block waits for its own
+// stores to complete before the arrival count that announces them.  A
+// device-scope fence would order plain stores too, but on gfx950 it writes
+// back and invalidates the whole L2 of the block's XCD, which costs far more
+// than the pass over the rows when every block pays it.
+__device__ __forceinline__ void st_dev(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_dev(const double *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// the result may go to host memory: written through at system scope
+__device__ __forceinline__ void st_sys(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+// every memory operation this wave issued has completed
+__device__ __forceinline__ void wait_stores() { __builtin_amdgcn_s_waitcnt(0); }
+
+// Called by every block after it stored its partial with st_dev (PS doubles:
+// the summed log term or w I, then the complex adjoint sums).  The last block
+// of each group adds the group's partials; the last group adds the group sums
+// and writes the result.
+template <int PS, int NT>
+__device__ __forceinline__ void finish(const StreamArgs &p, double log_scale) {
+    __shared__ unsigned s_last;
+    __shared__ double tot[2 * PS];
+    __shared__ double mv[PS];
+    __shared__ double s_c;
+    const int tid = threadIdx.x;
+    const int nbt = p.nb[0] + p.nb[1];
+    const int grp = (int)blockIdx.x / kFinishGroup;
+    const int g0 = grp * kFinishGroup;
+    const int gn = min(kFinishGroup, nbt - g0);
+    const int ngroups = (nbt + kFinishGroup - 1) / kFinishGroup;
+
+    wait_stores();
+    __syncthreads();
+    if (tid == 0) s_last = atomicAdd(&p.counters[1 + grp], 1u) == (unsigned)(gn - 1);
+    __syncthreads();
+    if (!s_last) return;
+
+    // group sums: data columns then MC columns, blocks in order (all loads of a
+    // column in flight at once; blocks outside the group or the segment add 0)
+    for (int col = tid; col < 2 * PS; col += NT) {
+        const int sg = col >= PS ? 1 : 0;
+        const int c = col - sg * PS;
+        double v[kFinishGroup];
+#pragma unroll
+        for (int i = 0; i < kFinishGroup; ++i)
+            v[i] = ld_dev(p.partials + (int64_t)(g0 + (i < gn ? i : gn - 1)) * PS + c);
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < kFinishGroup; ++i) {
+            const bool take = i < gn && ((g0 + i >= p.nb[0]) == (sg == 1));
+            s += take ? v[i] : 0.0;
+        }
+        st_dev(p.gsums + (int64_t)grp * 2 * PS + col, s);
+    }
+    if (tid == 0) __hip_atomic_store(&p.counters[1 + grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    wait_stores();
+    __syncthreads();
+    if (tid == 0) s_last = atomicAdd(&p.counters[0], 1u) == (unsigned)(ngroups - 1);
+    __syncthreads();
+    if (!s_last) return;
+
+    // totals over the groups: TPC threads per column, thread r adding groups
+    // r, r + TPC, ... in order (16 loads in flight), then the TPC sums of a
+    // column in thread order
+    constexpr int NCOL = 2 * PS;
+    constexpr int TPC = NT / NCOL > 0 ? NT / NCOL : 1;
+    __shared__ double part[NCOL * TPC];
+    for (int slot = tid; slot < NCOL * TPC; slot += NT) {
+        const int col = slot / TPC, r = slot % TPC;
+        double s = 0.0;
+        for (int gb = r; gb < ngroups; gb += 16 * TPC) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int gi = gb + u * TPC;
+                v[u] = ld_dev(p.gsums + (int64_t)(gi < ngroups ? gi : ngroups - 1) * NCOL + col);
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) s += gb + u * TPC < ngroups ? v[u] : 0.0;
+        }
+        part[slot] = s;
+    }
+    if (tid == 0) __hip_atomic_store(&p.counters[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    for (int col = tid; col < NCOL; col += NT) {
+        double s = 0.0;
+        for (int r = 0; r < TPC; ++r) s += part[col * TPC + r];
+        tot[col] = s;
+    }
+    __syncthreads();
+
+    // Eq. 2 form:  NLL = -sum ln I + N_D ln S,   c = N_D / (N_gen S)
+    // Eq. 3 form:  NLL = -sum ln I + S,          c = 1 / N_gen
+    // gradient     = 2 (-G + c H), H = sum w conj(A) z over MC rows, or with the
+    // MC matrix M (1/N_gen folded in): S = V^H M V and H replaced by M V, N_gen = 1
+    const int k = p.k;
+    const double *V = p.v_dev ? p.v_dev : p.v_arg;
+    if (p.gram) {
+        for (int a = tid; a < k; a += NT) {
+            double r = 0.0, i = 0.0;
+            for (int b = 0; b < k; ++b) {
+                const double mr = p.gram[2 * (a * k + b)], mi = p.gram[2 * (a * k + b) + 1];
+                r += mr * V[2 * b] - mi * V[2 * b + 1];
+                i += mr * V[2 * b + 1] + mi * V[2 * b];
+            }
+            mv[2 * a] = r;
+            mv[2 * a + 1] = i;
+        }
+        __syncthreads();
+    }
+    const double *td = tot;          // data: [0] sum log, [1 + i] G
+    const double *tm = tot + PS;     // MC:   [0] sum w I, [1 + i] H
+    const bool empty = !p.extended && p.nd_total == 0.0;
+    if (tid == 0) {
+        const double nd = p.nd_total;
+        const double sum_log = td[0] * log_scale;
+        double S, c;
+        if (p.gram) {
+            double s = 0.0;
+            for (int a = 0; a < k; ++a) s += V[2 * a] * mv[2 * a] + V[2 * a + 1] * mv[2 * a + 1];
+            S = s;                                  // Re V^H (M V)
+            c = p.extended ? 1.0 : nd / S;
+        } else {
+            S = tm[0] / p.n_gen;
+            c = p.extended ? 1.0 / p.n_gen : nd / tm[0];
+        }
+        double nll;
+        unsigned flags = 0;
+        if (empty) {
+            nll = 0.0;                              // empty product: ln L = 0
+            c = 0.0;
+        } else {
+            nll = p.extended ? -sum_log + S : -sum_log + nd * log(S);
+            if (!isfinite(nll) || (!p.extended && !(S > 0.0))) {
+                nll = INFINITY;
+                flags = 1;
+            }
+        }
+        st_sys(p.out, nll);
+        st_sys(p.out + 1 + 2 * k, (double)flags);
+        s_c = c;
+    }
+    __syncthreads();
+    const double c = s_c;
+    for (int i = tid; i < 2 * k; i += NT) {
+        const double h = p.gram ? mv[i] : tm[1 + i];
+        st_sys(p.out + 1 + i, empty ? 0.0 : 2.0 * (-td[1 + i] + c * h));
+    }
+    if (p.done) {
+        // the result reaches host memory before the sequence number that announces it
+        wait_stores();
+        __syncthreads();
+        if (tid == 0) __hip_atomic_store(p.done, p.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
 
 // One stage: U rows per lane group.
 template <typename T, int L, int C, int U, int SEG>
@@ -299,11 +464,10 @@ __global__ __launch_bounds__(NT) void nll_stream_kernel(StreamArgs p) {
     }
     __syncthreads();
 
-    // block partial, stored column-major ([column][block]) so the combine reads
-    // each column contiguously: column 0 the scalar sum, 1 + 2a + {0,1} the
+    // block partial [block][PS]: column 0 the scalar sum, 1 + 2a + {0,1} the
     // complex sums, a < ld
-    const int nbt = p.nb[0] + p.nb[1];
-    for (int idx = tid; idx < p.pstride; idx += NT) {
+    constexpr int PS = 1 + 2 * L * C;
+    for (int idx = tid; idx < PS; idx += NT) {
         double s = 0.0;
         if (idx == 0) {
             for (int w = 0; w < NW; ++w) s += red[w][0][0];
@@ -312,8 +476,9 @@ __global__ __launch_bounds__(NT) void nll_stream_kernel(StreamArgs p) {
             const int jj = a / C, c = a % C;
             for (int w = 0; w < NW; ++w) s += red[w][jj][1 + 2 * c + q];
         }
-        p.partials[(int64_t)idx * nbt + blockIdx.x] = s;
+        st_dev(p.partials + (int64_t)blockIdx.x * PS + idx, s);
     }
+    finish<PS, NT>(p, EventMath<T>::kLogScale);
 }
 
 template <typename T, int L, int C, int U>

@@ -54,3 +54,40 @@ def test_mlp_host_side_checks():
     assert b"shape" in lib.pwa_mlp_last_error(None)
     assert lib.pwa_mlp_destroy(None) == 0
     assert lib.pwa_mlp_set_params(None, None, 0) == 1
+
+
+def _fake_context(prec="f32", k=4):
+    """A Context object with no library handle, for the binding's own argument checks."""
+    import numpy as np
+    from paper_1108_5882_amd import _lib
+    c = _lib.Context.__new__(_lib.Context)
+    c.device, c.prec, c.k = 0, {"f32": _lib.F32, "f64": _lib.F64}[prec], k
+    c.real = np.float32 if prec == "f32" else np.float64
+    c.cplx = np.complex64 if prec == "f32" else np.complex128
+    c._borrowed, c._vbuf, c._obuf = {}, None, None
+    c.h = None
+    return c
+
+
+def test_binding_rejects_host_tensors_for_device_arguments():
+    """The device-side calls of the binding refuse CPU tensors, wrong dtypes and
+    wrong sizes before anything reaches the library (no device needed)."""
+    torch = pytest.importorskip("torch")
+    from paper_1108_5882_amd import _lib
+    c = _fake_context(k=4)
+    with pytest.raises(TypeError):
+        c.nll_grad_async(torch.zeros(8, dtype=torch.float64), torch.zeros(10, dtype=torch.float64))
+    with pytest.raises(TypeError):
+        c.nll_batch_async(torch.zeros((2, 8), dtype=torch.float64), torch.zeros((2, 10), dtype=torch.float64))
+    with pytest.raises(TypeError):
+        c._check_device_tensor(torch.zeros(8, dtype=torch.float32), "V_dev", torch.float64)
+    with pytest.raises(TypeError):
+        c.set_amplitudes("data", torch.zeros((3, 4), dtype=torch.complex64), borrow=True)
+    with pytest.raises(TypeError):
+        c.set_amplitudes("data", __import__("numpy").zeros((3, 4), dtype="complex64"), borrow=True)
+    # V of the wrong length for the synchronous calls
+    with pytest.raises(ValueError):
+        c._stage_v(__import__("numpy").ones(3, dtype=complex))
+    vp, op = c._stage_v(__import__("numpy").arange(4) * (1 + 1j))
+    assert list(c._vbuf) == [0, 0, 1, 1, 2, 2, 3, 3] and vp and op
+    assert _lib.BORROW == 2
