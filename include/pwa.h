@@ -141,6 +141,33 @@ pwa_status pwa_nll_grad(pwa_ctx *ctx, const double *V, double *nll, double *grad
  * not device memory of the context's device), PWA_E_STATE, PWA_E_HIP. */
 pwa_status pwa_nll_grad_async(pwa_ctx *ctx, const double *V_dev, double *out_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the NLL and
+ * gradient of pwa_nll_grad_async over caller-owned device samples, with no
+ * context, no allocation and no wait.  The kernel's workspace (block
+ * partials, group sums, arrival counters) is a static device array of
+ * PWA_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends; it bounds the launch's grid, not the sample sizes.
+ * The work goes to the current device.  Calls on one GPU share that array:
+ * calls that may overlap on one GPU (different streams, or threads) race and
+ * must be serialised by the caller; calls ordered on one stream are safe.
+ *   prec        amplitude precision of the samples
+ *   A_data      n_data rows, A_mc n_mc rows: device arrays in the library's
+ *               layout (row stride ld = pwa_layout_ld() for k, 16-byte aligned
+ *               base, zeros in columns k..ld-1; the zeros are not checked)
+ *   w_mc        device MC weights (precision of A) or NULL; n_gen <= 0: n_mc
+ *   extended    0: Eq. 2 form, 1: Eq. 3 form (the MC rows are streamed)
+ *   V_dev       device, 2k doubles; out_dev device, 2k + 2 doubles written as
+ *               by pwa_nll_grad_async; stream: hipStream_t or NULL
+ * The launch configuration is the one pwa_autotune chose for these sizes in
+ * this process, else the default.  Errors (host-side checks only, reported by
+ * pwa_last_error(NULL)): PWA_E_INVAL, PWA_E_UNSUPPORTED (k > PWA_MAX_K),
+ * PWA_E_HIP. */
+#define PWA_NOALLOC_SCRATCH_BYTES (2u << 20)
+pwa_status pwa_nll_grad_noalloc(pwa_prec prec, const void *A_data, int64_t n_data, const void *A_mc,
+                                int64_t n_mc, const void *w_mc, double n_gen, int32_t k, int64_t ld,
+                                int extended, const double *V_dev, double *out_dev, void *stream);
+
 /* NLL (and optionally gradients) for nv production vectors in one pass over
  * the events (many fits / many starting points, Section 2 on repeated fits).
  *   V      host, nv x 2k doubles (row b is V_b as above)

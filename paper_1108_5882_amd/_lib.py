@@ -33,7 +33,7 @@ EXPORTS = [
     "pwa_multi_get", "pwa_multi_autotune", "pwa_multi_last_error", "pwa_batch_fit",
     "pwa_mlp_param_count", "pwa_mlp_create", "pwa_mlp_destroy", "pwa_mlp_set_params", "pwa_mlp_get_params",
     "pwa_mlp_features", "pwa_mlp_targets", "pwa_mlp_predict", "pwa_mlp_loss_grad", "pwa_mlp_train",
-    "pwa_mlp_select", "pwa_mlp_last_error",
+    "pwa_mlp_select", "pwa_mlp_last_error", "pwa_nll_grad_noalloc",
 ]
 
 
@@ -134,6 +134,7 @@ def load(path: str = LIB_PATH):
         "pwa_mlp_loss_grad": [P, P, P, I32, ctypes.POINTER(ctypes.c_float), P],
         "pwa_mlp_train": [P, P, P, I64, P, I32, I32, ctypes.c_float, P, ctypes.POINTER(D)],
         "pwa_mlp_select": [P, P, I64, I32, P],
+        "pwa_nll_grad_noalloc": [ctypes.c_int, P, I64, P, I64, P, D, I32, I64, ctypes.c_int, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -165,6 +166,51 @@ def _stream_handle(stream) -> Optional[int]:
     if isinstance(stream, int):
         return stream
     return int(stream.cuda_stream)    # torch.cuda.Stream
+
+
+def nll_grad_noalloc(A_data, A_mc, V_dev, out_dev, w_mc=None, n_gen: Optional[float] = None,
+                     extended: bool = False, stream=None, k: Optional[int] = None):
+    """NLL and gradient over caller-owned GPU samples with no context and no
+    allocation (pwa_nll_grad_noalloc): A_data [n_d, ld], A_mc [n_m, ld] complex64
+    or complex128 GPU tensors in the library's layout (ld = layout width of k,
+    zero padding columns; k defaults to ld), w_mc matching real weights or None,
+    V_dev float64 [2k], out_dev float64 [2k + 2] (nll, grad[2k], flags).  The
+    kernel is enqueued on `stream` (torch.cuda.Stream, raw handle or None) of the
+    tensors' device; nothing waits."""
+    import torch
+    lib = load()
+    if A_data.dtype not in (torch.complex64, torch.complex128) or A_mc.dtype != A_data.dtype:
+        raise TypeError("A_data and A_mc must both be complex64 or both complex128")
+    prec = F32 if A_data.dtype == torch.complex64 else F64
+    dev = A_data.device
+    real = torch.float32 if prec == F32 else torch.float64
+    for t, name, dt in ((A_mc, "A_mc", A_data.dtype), (V_dev, "V_dev", torch.float64),
+                        (out_dev, "out_dev", torch.float64)) + (((w_mc, "w_mc", real),) if w_mc is not None else ()):
+        if not _is_torch(t) or not t.is_cuda or t.device != dev or t.dtype != dt:
+            raise TypeError(f"{name} must be a {dt} tensor on {dev}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+    if not A_data.is_cuda or not A_data.is_contiguous() or A_data.dim() != 2 or A_mc.dim() != 2:
+        raise ValueError("A_data and A_mc must be contiguous 2-d GPU tensors")
+    ld = A_data.shape[1]
+    if A_mc.shape[1] != ld:
+        raise ValueError("A_data and A_mc must have the same row width")
+    k = ld if k is None else int(k)
+    if V_dev.numel() != 2 * k or out_dev.numel() != 2 * k + 2:
+        raise ValueError("V_dev must hold 2k and out_dev 2k + 2 doubles")
+    if w_mc is not None and w_mc.numel() != A_mc.shape[0]:
+        raise ValueError("w_mc must hold one weight per MC row")
+    s = _stream_handle(stream)
+    with torch.cuda.device(dev):
+        st = lib.pwa_nll_grad_noalloc(prec, ctypes.c_void_p(A_data.data_ptr()), A_data.shape[0],
+                                      ctypes.c_void_p(A_mc.data_ptr()), A_mc.shape[0],
+                                      None if w_mc is None else ctypes.c_void_p(w_mc.data_ptr()),
+                                      float(n_gen or 0.0), k, ld, int(bool(extended)),
+                                      ctypes.c_void_p(V_dev.data_ptr()), ctypes.c_void_p(out_dev.data_ptr()),
+                                      None if s is None else ctypes.c_void_p(s))
+    if st != OK:
+        msg = lib.pwa_last_error(None)
+        raise PwaError(st, msg.decode() if msg else "")
 
 
 class Context:
