@@ -44,33 +44,75 @@ def kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def stored_traffic(units_per_launch):
+def stored_traffic(units_per_launch, kernel: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or None
-    when the kernel source changed since the counters were taken."""
+    when the kernel source or the launch configuration differs from the one
+    the counters were taken on."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha256_16") != kernel_hash() or t.get("units_per_launch") != units_per_launch:
+    if (t.get("kernel_sha256_16") != kernel_hash() or t.get("units_per_launch") != units_per_launch
+            or t.get("kernel") != kernel):
         return None
     return t.get("hbm_bytes_per_launch")
 
 
+def host_threads() -> int:
+    """Threads the OpenMP oracle runs on: OMP_NUM_THREADS, else the CPUs this process may use."""
+    try:
+        n = int(os.environ.get("OMP_NUM_THREADS", "0"))
+    except ValueError:
+        n = 0
+    return n if n > 0 else len(os.sched_getaffinity(0))
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(sample, V, budget_s: float):
+    """The FP64 oracle on the host: its chunked form (fixed 65536-row chunks, the
+    result independent of the thread count) on one thread and on all the threads
+    this process may use, each for about budget_s / 2 seconds."""
+    import numpy as np
+
     import oracle
-    evals, t0 = 0, time.perf_counter()
-    while True:
-        oracle.nll_grad(sample.A_data, sample.A_mc, V)
-        evals += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = time.perf_counter() - t0
-    units = evals * (sample.A_data.shape[0] + sample.A_mc.shape[0])
-    return {"value": units / dt, "unit": "event-evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{evals} FP64 NLL+grad evaluations of the full workload "
-                      f"({sample.A_data.shape[0]} data + {sample.A_mc.shape[0]} MC rows), "
-                      f"{dt:.1f} s, one thread"}
+    Ad = np.ascontiguousarray(sample.A_data, dtype=np.complex128)
+    Am = np.ascontiguousarray(sample.A_mc, dtype=np.complex128)
+    rows = Ad.shape[0] + Am.shape[0]
+    out = {}
+    for threads in (1, host_threads()):
+        oracle.nll_grad_chunked(Ad, Am, V, threads=threads)
+        evals, t0 = 0, time.perf_counter()
+        while True:
+            oracle.nll_grad_chunked(Ad, Am, V, threads=threads)
+            evals += 1
+            if time.perf_counter() - t0 >= budget_s / 2:
+                break
+        dt = time.perf_counter() - t0
+        out[threads] = (evals * rows / dt, evals, dt)
+    n = host_threads()
+    v1, e1, d1 = out[1]
+    vn, en, dn = out[n]
+    return {"value": vn, "unit": "event-evals/s", "cores": n, "kind": "oracle",
+            "sample": f"FP64 NLL+grad evaluations of the full workload ({Ad.shape[0]} data + {Am.shape[0]} MC "
+                      f"rows): {en} in {dn:.1f} s on {n} threads, {e1} in {d1:.1f} s on one thread",
+            "single_thread": {"value": v1, "cores": 1},
+            "host": {"cpu": cpu_model(), "threads_available": len(os.sched_getaffinity(0))}}
+
+
+def kernel_name(cfg) -> str:
+    return "nll_stream_kernel<float, L=%d, C=%d, U=%d>, %d blocks/CU" % (
+        cfg["lanes_per_row"], cfg["complex_per_lane"], cfg["rows_per_stage"], cfg["blocks_per_cu"])
 
 
 def main():
@@ -85,6 +127,9 @@ def main():
     ap.add_argument("--probe", action="store_true",
                     help="for HBM counter runs: a few evaluations plus a plain device copy of the "
                          "same byte count (the counter scale reference); prints no JSON")
+    ap.add_argument("--cfg", default="",
+                    help="lanes_per_row,complex_per_lane,rows_per_stage,blocks_per_cu of the single-V kernel "
+                         "instead of autotuning (for counter runs on the configuration a bench run chose)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the likelihood path has no multi-GPU mode "
@@ -109,8 +154,13 @@ def main():
     ctx = Context(0, "f32", stream=stream)
     ctx.set_amplitudes("data", s.A_data)
     ctx.set_amplitudes("mc", s.A_mc)
-    cfg, tune_ms = ctx.autotune(reps=5)
-    log(f"autotuned stream configuration {cfg}: {tune_ms * 1e3:.1f} us")
+    if args.cfg:
+        ctx.set_stream_cfg(*[int(x) for x in args.cfg.split(",")])
+        cfg = ctx.stream_cfg()
+        log(f"stream configuration {cfg} (given)")
+    else:
+        cfg, tune_ms = ctx.autotune(reps=5)
+        log(f"autotuned stream configuration {cfg}: {tune_ms * 1e3:.1f} us")
     for _ in range(args.warmup):
         ctx.nll_grad(V)
     torch.cuda.synchronize()
@@ -122,7 +172,7 @@ def main():
             dst.copy_(src)
             ctx.nll_grad(V)
         torch.cuda.synchronize()
-        log(f"probe: 5 evaluations and 5 copies of {nbytes} bytes")
+        log(f"probe: 5 evaluations of {kernel_name(cfg)} and 5 copies of {nbytes} bytes")
         return
 
     ctx.set_timing(True)
@@ -144,14 +194,14 @@ def main():
 
     alg_bytes = units * 8 * k            # FP32 complex amplitudes read once per event
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
-    traffic = stored_traffic(units)
+    kernel = kernel_name(cfg)
+    traffic = stored_traffic(units, kernel)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "nll_stream_kernel<float, L=%d, C=%d, U=%d>, %d blocks/CU"
-                      % (cfg["lanes_per_row"], cfg["complex_per_lane"], cfg["rows_per_stage"],
-                         cfg["blocks_per_cu"]),
+            "kernel": kernel,
             "kernel_ms": k_ms,
-            "alg_bytes_per_launch": alg_bytes}
+            "alg_bytes_per_launch": alg_bytes,
+            "per_evaluation_frac": alg_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
     rec = {
         "metric": METRIC,

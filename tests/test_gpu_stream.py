@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import synth
-from tests.tolerance import TOL, errors, reference
+from tests.tolerance import TOL, errors, reference, reference_fast
 
 pytestmark = pytest.mark.gpu
 
@@ -97,6 +97,27 @@ def test_config_k4_fp64_full(pwa):
             e_n, e_g = errors(reference(s.A_data, s.A_mc, v), nll, grad)
             _say(f"  e_nll={e_n:.2e} e_grad={e_g:.2e}")
             assert e_n < 1e-12 and e_g < 1e-12
+
+
+def test_config_k16_fp64_full(pwa):
+    """K = 16, 10^6 data and 5 x 10^6 MC amplitudes in FP64 (an FP64 context):
+    1e-12 at the single-V workload's full size (plain FP64 lane and block sums)."""
+    _say("case cfg K=16 fp64 full size")
+    s = synth.make_sample(1, dtype=np.complex128)
+    V = synth.eval_vectors(1, 2, s.k)
+    with _ctx(pwa, "f64") as c:
+        c.set_amplitudes("data", s.A_data)
+        c.set_amplitudes("mc", s.A_mc)
+        for v in list(V) + [s.V_true]:
+            nll, grad = c.nll_grad(v)
+            e_n, e_g = errors(reference_fast(s.A_data, s.A_mc, v), nll, grad)
+            _say(f"  e_nll={e_n:.2e} e_grad={e_g:.2e}")
+            assert e_n < 1e-12 and e_g < 1e-12
+        c.set_mc_mode("gram")
+        nll, grad = c.nll_grad(V[0])
+        e_n, e_g = errors(reference_fast(s.A_data, s.A_mc, V[0]), nll, grad)
+        _say(f"  gram e_nll={e_n:.2e} e_grad={e_g:.2e}")
+        assert e_n < 1e-12 and e_g < 1e-12
 
 
 @pytest.mark.parametrize("scale", [0.05, 1.0])
