@@ -231,17 +231,31 @@ pwa_status pwa_nll_batch_async(pwa_ctx *ctx, int32_t nv, const double *V_dev, do
  * event with z = 0, or S <= 0; H then holds non-finite values), PWA_E_HIP. */
 pwa_status pwa_hessian(pwa_ctx *ctx, const double *V, double *H);
 
+/* Parameters the batched minimiser works in (Section 4, "Fits with complex
+ * parameters": minimisers see real numbers, and both representations of a
+ * complex parameter have their issues).
+ *   PWA_PARAM_CARTESIAN  (Re V_a, Im V_a) per wave, unbounded.
+ *   PWA_PARAM_POLAR      (|V_a|, arg V_a) per wave with the lower bound
+ *                        |V_a| >= rmin kept by projected steps, periodic phases
+ *                        wrapped into [-pi, pi] after each accepted step, and
+ *                        arg V_0 held at 0 (the likelihood does not depend on
+ *                        the global phase). */
+typedef enum { PWA_PARAM_CARTESIAN = 0, PWA_PARAM_POLAR = 1 } pwa_param;
+
 /* Minimise the NLL from nv starting vectors at once on the context's samples
  * (multi-start, Section 2): every iteration evaluates all trial vectors with
- * the matrix-core pass of pwa_nll_batch (split 2) and advances one device
- * L-BFGS state per vector (two-loop recursion, history 8, Armijo
- * backtracking); the iteration is captured in a HIP graph and replayed
- * `iters` times.  Outputs (host, any may be NULL): V nv x 2k accepted points,
- * nll[nv] their NLL, status[nv] (0 running, 1 converged, 2 step underflow),
- * avg_ms time per iteration.  FP32 contexts, k <= 48.  Errors as
- * pwa_nll_batch. */
-pwa_status pwa_batch_fit(pwa_ctx *ctx, int32_t nv, const double *V0, int32_t iters, double *V,
-                         double *nll, int32_t *status, double *avg_ms);
+ * the matrix-core pass of pwa_nll_batch with split 3 (small coherent sums
+ * recomputed exactly: NLL and gradient within 1e-6 of the oracle's) and
+ * advances one device L-BFGS state per vector (two-loop recursion, history 8,
+ * Armijo backtracking) in the parameters `param` selects (rmin: the polar
+ * magnitude bound, >= 0; ignored for PWA_PARAM_CARTESIAN); the iteration is
+ * captured in a HIP graph and replayed `iters` times.  Outputs (host, any may
+ * be NULL): V nv x 2k accepted points as (Re V_a, Im V_a) (in polar form with
+ * V_0 real and non-negative), nll[nv] their NLL, status[nv] (0 running,
+ * 1 converged, 2 step underflow), avg_ms time per iteration.  FP32 contexts,
+ * k <= 48.  Errors as pwa_nll_batch, PWA_E_INVAL for a bad param or rmin. */
+pwa_status pwa_batch_fit(pwa_ctx *ctx, int32_t nv, const double *V0, int32_t iters, pwa_param param,
+                         double rmin, double *V, double *nll, int32_t *status, double *avg_ms);
 
 /* Status flags of the last synchronous evaluation (0 = none). */
 pwa_status pwa_last_flags(pwa_ctx *ctx, uint32_t *flags);

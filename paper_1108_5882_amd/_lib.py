@@ -116,7 +116,7 @@ def load(path: str = LIB_PATH):
         "pwa_get_stream_cfg": [P, ctypes.POINTER(StreamCfg)],
         "pwa_set_stream_cfg": [P, ctypes.POINTER(StreamCfg)],
         "pwa_autotune": [P, I32, ctypes.POINTER(StreamCfg), ctypes.POINTER(D)],
-        "pwa_batch_fit": [P, I32, P, I32, P, P, P, ctypes.POINTER(D)],
+        "pwa_batch_fit": [P, I32, P, I32, ctypes.c_int, D, P, P, P, ctypes.POINTER(D)],
         "pwa_multi_create": [ctypes.POINTER(P), ctypes.c_int, I32, ctypes.POINTER(FitDesc), P],
         "pwa_multi_destroy": [P],
         "pwa_multi_eval": [P, P, P, P],
@@ -438,8 +438,10 @@ class Context:
         self._check(self.lib.pwa_nll_batch_async(self.h, nv, ctypes.c_void_p(V_dev.data_ptr()),
                                                  ctypes.c_void_p(out_dev.data_ptr()), int(split)))
 
-    def batch_fit(self, V0, iters: int):
-        """L-BFGS from every row of V0 [nv, k] (complex) at once; returns
+    def batch_fit(self, V0, iters: int, polar: bool = False, rmin: float = 0.0):
+        """L-BFGS from every row of V0 [nv, k] (complex) at once, each iteration one
+        split-3 matrix-core evaluation of all trial points; in (Re, Im) or, with
+        polar, in (|V|, arg V) with |V| >= rmin and arg V_0 = 0.  Returns
         (V [nv, k] complex, nll [nv], status [nv], ms per iteration)."""
         V0 = np.asarray(V0)
         v = np.empty((V0.shape[0], 2 * V0.shape[1]))
@@ -448,8 +450,8 @@ class Context:
         nll = np.zeros(V0.shape[0])
         st = np.zeros(V0.shape[0], dtype=np.int32)
         ms = ctypes.c_double()
-        self._check(self.lib.pwa_batch_fit(self.h, V0.shape[0], _ptr(v), int(iters), _ptr(out), _ptr(nll),
-                                           _ptr(st), ctypes.byref(ms)))
+        self._check(self.lib.pwa_batch_fit(self.h, V0.shape[0], _ptr(v), int(iters), int(bool(polar)), float(rmin),
+                                           _ptr(out), _ptr(nll), _ptr(st), ctypes.byref(ms)))
         return out[:, 0::2] + 1j * out[:, 1::2], nll, st, ms.value
 
     def last_flags(self) -> int:

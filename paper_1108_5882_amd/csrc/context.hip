@@ -447,6 +447,29 @@ pwa_status batch_setup(pwa_ctx *ctx, int32_t nv, BatchArgs &a, int *gpad, bool a
     return PWA_OK;
 }
 
+// Row norms of the data rows and flag words for the exact recomputation of
+// small coherent sums (split 3) of nv vectors; with alloc = false nothing is
+// allocated or launched (PWA_E_STATE if they are missing).
+pwa_status refine_setup(pwa_ctx *ctx, int32_t nv, BatchArgs &a, bool alloc) {
+    const int k = ctx->k;
+    pwa_status st;
+    if (!alloc && !ctx->rnorm_valid)
+        return fail(ctx, PWA_E_STATE, "row norms not prepared: call pwa_nll_batch with split 3 first");
+    if (!ctx->rnorm_valid) {
+        if (ctx->b_rnorm) (void)hipFree(ctx->b_rnorm);
+        ctx->b_rnorm = nullptr;
+        PWA_HIP(ctx, hipMalloc(&ctx->b_rnorm, sizeof(float) * (size_t)a.n[0]), "hipMalloc(row norms)");
+        PWA_HIP(ctx, launch_rownorm(a.A[0], a.n[0], a.ld, k, ctx->b_rnorm, ctx->stream), "row norm launch");
+        ctx->rnorm_valid = true;
+    }
+    if ((st = reserve(ctx, alloc, &ctx->b_flags, &ctx->flags_cap,
+                      sizeof(unsigned long long) * batch_flag_words(a.n[0], nv, k), "flags")))
+        return st;
+    a.rnorm = ctx->b_rnorm;
+    a.flags = static_cast<unsigned long long *>(ctx->b_flags);
+    return PWA_OK;
+}
+
 // Batched NLL (and gradient) of nv host vectors on the matrix cores: device
 // weights from V, the matrix-core pass (with refine: flags for data events with
 // small coherent sums, then their exact terms), the per-vector combine.
@@ -464,20 +487,7 @@ pwa_status batch_launch(pwa_ctx *ctx, int32_t nv, const double *V_dev, double *o
     a.out = out_dev;
     a.ostride = 2 * k + 2;
     if (refine && a.n[0] > 0) {
-        if (!alloc && !ctx->rnorm_valid)
-            return fail(ctx, PWA_E_STATE, "row norms not prepared: call pwa_nll_batch with split 3 first");
-        if (!ctx->rnorm_valid) {
-            if (ctx->b_rnorm) (void)hipFree(ctx->b_rnorm);
-            ctx->b_rnorm = nullptr;
-            PWA_HIP(ctx, hipMalloc(&ctx->b_rnorm, sizeof(float) * (size_t)a.n[0]), "hipMalloc(row norms)");
-            PWA_HIP(ctx, launch_rownorm(a.A[0], a.n[0], a.ld, k, ctx->b_rnorm, ctx->stream), "row norm launch");
-            ctx->rnorm_valid = true;
-        }
-        if ((st = reserve(ctx, alloc, &ctx->b_flags, &ctx->flags_cap,
-                          sizeof(unsigned long long) * batch_flag_words(a.n[0], nv, k), "flags")))
-            return st;
-        a.rnorm = ctx->b_rnorm;
-        a.flags = static_cast<unsigned long long *>(ctx->b_flags);
+        if ((st = refine_setup(ctx, nv, a, alloc)) != PWA_OK) return st;
     } else {
         refine = false;
     }
@@ -582,10 +592,13 @@ hipError_t stage_rows(void *dst, size_t dst_pitch, const void *src, size_t src_p
 
 extern "C" {
 
-pwa_status pwa_batch_fit(pwa_ctx *ctx, int32_t nv, const double *V0, int32_t iters, double *V,
-                         double *nll, int32_t *status, double *avg_ms) {
+pwa_status pwa_batch_fit(pwa_ctx *ctx, int32_t nv, const double *V0, int32_t iters, pwa_param param, double rmin,
+                         double *V, double *nll, int32_t *status, double *avg_ms) {
     if (!ctx) return fail(nullptr, PWA_E_INVAL, "null context");
     if (nv < 1 || !V0 || iters < 0) return fail(ctx, PWA_E_INVAL, "bad arguments");
+    if (param != PWA_PARAM_CARTESIAN && param != PWA_PARAM_POLAR) return fail(ctx, PWA_E_INVAL, "bad parametrisation");
+    if (!(rmin >= 0.0) || !std::isfinite(rmin)) return fail(ctx, PWA_E_INVAL, "rmin must be finite and >= 0");
+    const bool polar = param == PWA_PARAM_POLAR;
     if (ctx->prec != PWA_F32) return fail(ctx, PWA_E_UNSUPPORTED, "batched fits need an FP32 context");
     if (ctx->k > kMultiMaxLd) return fail(ctx, PWA_E_UNSUPPORTED, "batched fits need k <= %d", kMultiMaxLd);
     const int k = ctx->k;
@@ -596,11 +609,28 @@ pwa_status pwa_batch_fit(pwa_ctx *ctx, int32_t nv, const double *V0, int32_t ite
     int gpad = 0;
     pwa_status st = batch_setup(ctx, nv, a, &gpad);
     if (st != PWA_OK) return st;
+    if (a.n[0] > 0 && (st = refine_setup(ctx, nv, a, true)) != PWA_OK) return st;
     // L-BFGS states: the matrix-core pass reads each vector's trial point in place
+    // (xt, or in polar form the V it stands for, vt)
     std::vector<LbfgsState> hs(nv);
     for (int v = 0; v < nv; ++v) {
         std::memset(&hs[v], 0, sizeof(LbfgsState));
-        for (int i = 0; i < 2 * k; ++i) hs[v].xt[i] = V0[(size_t)v * 2 * k + i];
+        const double *v0 = V0 + (size_t)v * 2 * k;
+        if (!polar) {
+            for (int i = 0; i < 2 * k; ++i) hs[v].xt[i] = v0[i];
+            continue;
+        }
+        // polar start: the global phase that makes V_0 real and non-negative, then
+        // magnitudes (at least rmin) and phases
+        const double ph0 = std::atan2(v0[1], v0[0]);
+        for (int b = 0; b < k; ++b) {
+            const double r = std::max(std::hypot(v0[2 * b], v0[2 * b + 1]), rmin);
+            const double ph = b == 0 ? 0.0 : std::remainder(std::atan2(v0[2 * b + 1], v0[2 * b]) - ph0, 2.0 * M_PI);
+            hs[v].xt[2 * b] = r;
+            hs[v].xt[2 * b + 1] = ph;
+            hs[v].vt[2 * b] = r * std::cos(ph);
+            hs[v].vt[2 * b + 1] = r * std::sin(ph);
+        }
     }
     LbfgsState *d_states = nullptr;
     double *d_out = nullptr;
@@ -609,7 +639,7 @@ pwa_status pwa_batch_fit(pwa_ctx *ctx, int32_t nv, const double *V0, int32_t ite
     hipError_t e = hipMalloc(&d_out, sizeof(double) * ostride * nv);
     if (e == hipSuccess)
         e = hipMemcpyAsync(d_states, hs.data(), sizeof(LbfgsState) * nv, hipMemcpyHostToDevice, ctx->stream);
-    a.V = d_states[0].xt;
+    a.V = polar ? d_states[0].vt : d_states[0].xt;
     a.vstride = sizeof(LbfgsState) / sizeof(double);
     a.out = d_out;
     a.ostride = ostride;
@@ -617,10 +647,15 @@ pwa_status pwa_batch_fit(pwa_ctx *ctx, int32_t nv, const double *V0, int32_t ite
     hipGraphExec_t exec = nullptr;
     if (e == hipSuccess) e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
+        // the split-3 pass: matrix-core sums with small coherent sums flagged, their
+        // exact recomputation, the combine, then one L-BFGS update per vector
+        const bool refine = a.n[0] > 0;
         hipError_t ec = launch_batch_weights(a, ctx->stream);
-        if (ec == hipSuccess) ec = launch_batch(a, false, ctx->stream);
+        if (ec == hipSuccess) ec = launch_batch(a, refine, ctx->stream);
+        if (ec == hipSuccess && refine) ec = launch_batch_refine(a, ctx->stream);
         if (ec == hipSuccess) ec = launch_batch_combine(a, ctx->stream);
-        if (ec == hipSuccess) ec = launch_lbfgs(nullptr, k, d_out, ostride, d_states, nv, 8, 1e-4, 1e-12, ctx->stream);
+        if (ec == hipSuccess)
+            ec = launch_lbfgs(nullptr, k, d_out, ostride, d_states, nv, 8, 1e-4, 1e-12, ctx->stream, polar ? 1 : 0, rmin);
         e = hipStreamEndCapture(ctx->stream, &graph);
         if (ec != hipSuccess) e = ec;
     }
@@ -648,8 +683,14 @@ pwa_status pwa_batch_fit(pwa_ctx *ctx, int32_t nv, const double *V0, int32_t ite
     if (e != hipSuccess) return hip_fail(ctx, e, "batched fit");
     for (int v = 0; v < nv; ++v) {
         const bool started = hs[v].phase != 0;
-        if (V)
-            for (int i = 0; i < 2 * k; ++i) V[(size_t)v * 2 * k + i] = started ? hs[v].x[i] : hs[v].xt[i];
+        const double *p = started ? hs[v].x : hs[v].xt;
+        if (V && !polar)
+            for (int i = 0; i < 2 * k; ++i) V[(size_t)v * 2 * k + i] = p[i];
+        if (V && polar)
+            for (int b = 0; b < k; ++b) {
+                V[(size_t)v * 2 * k + 2 * b] = p[2 * b] * std::cos(p[2 * b + 1]);
+                V[(size_t)v * 2 * k + 2 * b + 1] = p[2 * b] * std::sin(p[2 * b + 1]);
+            }
         if (nll) nll[v] = started ? hs[v].f : NAN;
         if (status) status[v] = hs[v].status;
     }

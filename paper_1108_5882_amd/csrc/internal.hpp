@@ -191,8 +191,10 @@ struct MultiArgs {
 };
 
 // L-BFGS state of one fit (device memory).
+// Parameters x are (Re V_a, Im V_a) per wave, or in polar mode (|V_a|, arg V_a)
+// with arg V_0 held at 0; vt is the trial point as V (Re, Im) in polar mode.
 struct LbfgsState {
-    double x[kLbfgsMaxN], g[kLbfgsMaxN], xt[kLbfgsMaxN], d[kLbfgsMaxN];
+    double x[kLbfgsMaxN], g[kLbfgsMaxN], xt[kLbfgsMaxN], d[kLbfgsMaxN], vt[kLbfgsMaxN];
     double S[kLbfgsMaxHist][kLbfgsMaxN], Y[kLbfgsMaxHist][kLbfgsMaxN], rho[kLbfgsMaxHist];
     double f, alpha, gtd;
     int32_t head, count, phase, iter, status, nbacktrack;
@@ -204,9 +206,13 @@ int multi_rows_per_tile(int64_t ld);         // rows one wave covers per tile
 hipError_t launch_multi_eval(const MultiArgs &args, int blocks, hipStream_t stream);
 // One L-BFGS update per fit: fit f has 2 * k_f parameters (k_f = fits[f].k, or
 // k_all when fits is null) and its result [nll, grad] at out + f * ostride.
+// polar: parameters (|V_a|, arg V_a) with |V_a| >= rmin (projected steps),
+// arg V_0 fixed at 0 and phases wrapped into [-pi, pi] after each accepted
+// step; the evaluation reads vt.  Otherwise (Re V_a, Im V_a) and the
+// evaluation reads xt.
 hipError_t launch_lbfgs(const MultiFit *fits, int k_all, const double *out, int64_t ostride,
                         LbfgsState *states, int nfits, int m, double c1, double ftol,
-                        hipStream_t stream);
+                        hipStream_t stream, int polar = 0, double rmin = 0.0);
 
 // Copies n rows of `width` bytes from src (rows src_pitch apart; host or
 // device memory per kind) to dst (rows dst_pitch apart, the bytes past width

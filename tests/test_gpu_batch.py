@@ -17,6 +17,7 @@ whose coherent sum is small against the bound |z| <= |V| |A_i| (|z| < c |V|
 and recomputed in FP64 by a second kernel; it meets 1e-6 for every vector.  Split 0 (one exact streaming
 pass per vector) meets 1e-6 everywhere and is tested here too.
 """
+import math
 import sys
 
 import numpy as np
@@ -215,11 +216,13 @@ def test_batch_edge_cases(pwa):
 
 
 def test_batch_fit_descends_to_the_minimum(pwa):
-    """Device multi-start L-BFGS on the matrix-core pass (one graph per iteration).
+    """Device multi-start L-BFGS on the matrix-core pass with exact recomputation
+    of small coherent sums (split 3; one graph per iteration).
 
-    Every start ends below its starting NLL; the reported NLL is the split-2 value at
-    the returned V (oracle within the stated NLL error); the best start reaches the
-    minimum of an FP64 fit on the oracle (scipy L-BFGS-B) within the split-2 noise.
+    Every start ends below its starting NLL; the reported NLL is the split-3
+    value at the returned V (oracle within 1e-6 of the term scale); the best
+    start reaches the minimum of an FP64 fit on the oracle (SciPy L-BFGS-B)
+    within 1e-6 of the term scale.
     """
     import scipy.optimize as so
     k, nv = 8, 48
@@ -232,9 +235,9 @@ def test_batch_fit_descends_to_the_minimum(pwa):
         V, nll, st, ms = c.batch_fit(V0, 150)
         # zero iterations: the starts come back unevaluated
         Vz, nz, sz, _ = c.batch_fit(V0[:3], 0)
-        # one iteration: the starts, evaluated by the matrix-core pass
+        # one iteration: the starts, evaluated by the split-3 pass
         V1, n1, _, _ = c.batch_fit(V0[:5], 1)
-        nb, _ = c.nll_batch(V0[:5], split=2)
+        nb, _ = c.nll_batch(V0[:5], split=3)
     assert np.array_equal(Vz, V0[:3]) and np.all(np.isnan(nz)) and np.all(sz == 0)
     assert np.array_equal(V1, V0[:5]) and np.allclose(n1, nb, rtol=0, atol=1e-9 * np.abs(nb).max())
     assert set(np.unique(st)) <= {0, 1, 2}
@@ -244,7 +247,7 @@ def test_batch_fit_descends_to_the_minimum(pwa):
     assert np.all(f < f0)
     for b in range(nv):
         e_n, _ = errors(reference(s.A_data, s.A_mc, V[b]), nll[b], np.zeros(2 * k))
-        assert e_n < STATED["nll_max"], b
+        assert e_n < 1e-6, b
     best = int(np.argmin(f))
 
     def fun(x):
@@ -256,4 +259,56 @@ def test_batch_fit_descends_to_the_minimum(pwa):
     res = so.minimize(fun, x0, jac=True, method="L-BFGS-B", options=dict(maxiter=500, ftol=1e-15, gtol=1e-10))
     scale = reference(s.A_data, s.A_mc, V[best])["s_nll"]
     _say(f"  best start NLL {f[best]:.6f}, FP64 minimum {res.fun:.6f}, gap {(f[best] - res.fun) / scale:.2e} scaled")
+    assert (f[best] - res.fun) / scale < 1e-6
+
+
+def test_batch_fit_polar(pwa):
+    """The batched minimiser in polar parameters (|V_a| >= rmin, periodic phases,
+    arg V_0 = 0): it follows the FP64 reference L-BFGS in the same parameters
+    for the first iterations, and its best start reaches the Cartesian FP64
+    minimum within 1e-5 of the term scale; every returned V has V_0 real."""
+    import scipy.optimize as so
+
+    from oracle.lbfgs import LbfgsOracle
+    k, nv = 8, 32
+    s = synth.make_sample(2, n_data=4000, n_mc=16000, k=k, seed=5)
+    V0 = synth.eval_vectors(2, nv, k, seed=8)
+    _say("case batch_fit polar k=8 nv=32")
+    T = 10
+    with pwa.Context(0, "f32") as c:
+        c.set_amplitudes("data", s.A_data)
+        c.set_amplitudes("mc", s.A_mc)
+        VT, fT, _, _ = c.batch_fit(V0, T, polar=True)
+        V, nll, st, ms = c.batch_fit(V0, 300, polar=True)
+        # a bound above every start magnitude: every returned magnitude respects it
+        rmin = 1.01 * float(np.max(np.abs(V0)))
+        Vb, _, _, _ = c.batch_fit(V0[:4], 40, polar=True, rmin=rmin)
+    assert np.all(np.abs(Vb) >= rmin * (1 - 1e-12))
+    assert np.all(V[:, 0].imag == 0.0) and np.all(V[:, 0].real >= 0.0)
+
+    def fun(x):
+        return oracle.nll_grad(s.A_data, s.A_mc, x[0::2] + 1j * x[1::2])
+    for b in range(3):
+        v0 = V0[b]
+        ph0 = math.atan2(v0[0].imag, v0[0].real)
+        p0 = np.empty(2 * k)
+        p0[0::2] = np.abs(v0)
+        p0[1::2] = [0.0] + [math.remainder(math.atan2(z.imag, z.real) - ph0, 2 * math.pi) for z in v0[1:]]
+        ref = LbfgsOracle(fun, p0, polar=True)
+        for _ in range(T):
+            ref.step()
+        Vr = ref.x[0::2] * np.exp(1j * ref.x[1::2])
+        scale = reference(s.A_data, s.A_mc, Vr)["s_nll"]
+        _say(f"  start {b}: after {T} steps f gpu {fT[b]:.10g} ref {ref.f:.10g} "
+             f"dV {np.max(np.abs(VT[b] - Vr)) / np.max(np.abs(Vr)):.2e}")
+        assert abs(fT[b] - ref.f) < 1e-6 * scale
+        assert np.max(np.abs(VT[b] - Vr)) < 1e-4 * np.max(np.abs(Vr))
+    f = np.array([oracle.nll_grad(s.A_data, s.A_mc, V[b])[0] for b in range(nv)])
+    best = int(np.argmin(f))
+    x0 = np.empty(2 * k)
+    x0[0::2], x0[1::2] = V[best].real, V[best].imag
+    res = so.minimize(fun, x0, jac=True, method="L-BFGS-B", options=dict(maxiter=500, ftol=1e-15, gtol=1e-10))
+    scale = reference(s.A_data, s.A_mc, V[best])["s_nll"]
+    _say(f"  polar: {ms:.3f} ms / iteration; status {np.bincount(st, minlength=3)}; best {f[best]:.6f}, "
+         f"FP64 minimum {res.fun:.6f}, gap {(f[best] - res.fun) / scale:.2e} scaled")
     assert (f[best] - res.fun) / scale < 1e-5
