@@ -25,15 +25,17 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(_HERE, "oracle.c")
+KIN_SRC = os.path.join(_HERE, "kin.c")
 LIB = os.path.join(_HERE, "liboracle.so")
 CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math", "-ffp-contract=off", "-fopenmp"]
 
 
-def build(force: bool = True, src: str = SRC, out: str = LIB) -> str:
-    """Compile the oracle with gcc (no fast-math: the compensated sums need IEEE order)."""
+def build(force: bool = True, src: str = SRC, out: str = LIB, kin_src: str = KIN_SRC) -> str:
+    """Compile the oracle (oracle.c and kin.c) with gcc (no fast-math: the
+    compensated sums need IEEE order)."""
     if force or not os.path.exists(out):
         tmp = out + ".tmp"
-        subprocess.run(["gcc", *CFLAGS, src, "-o", tmp, "-lm"], check=True)
+        subprocess.run(["gcc", *CFLAGS, src, kin_src, "-o", tmp, "-lm"], check=True)
         os.replace(tmp, out)
     return out
 
@@ -62,6 +64,11 @@ class Oracle:
             lib.orc_nll_grad_chunked.argtypes = [I64, P, I64, I64, P, I64, P, D, I32, P, ctypes.c_int,
                                                  ctypes.c_int, P, P, P]
             fns.append(lib.orc_nll_grad_chunked)
+        self.has_kin = hasattr(lib, "orc_kin_nll_grad")
+        if self.has_kin:
+            lib.orc_kin_amplitudes.argtypes = [I64, P, I32, P, P, P]
+            lib.orc_kin_nll_grad.argtypes = [I64, P, I64, P, P, D, I32, P, P, P, ctypes.c_int, P, P, P]
+            fns += [lib.orc_kin_amplitudes, lib.orc_kin_nll_grad]
         for f in fns:
             f.restype = ctypes.c_int
         self.lib = lib
@@ -119,6 +126,36 @@ class Oracle:
             d = dict(sum_log=pr[0], s_raw=pr[1], GD=pr[2:2 + 2 * k].copy(), HM=pr[2 + 2 * k:].copy())
             return float(nll[0]), grad, d
         return float(nll[0]), grad
+
+    def kin_amplitudes(self, mx, spins, res) -> np.ndarray:
+        """A [n, k] complex: BW_a(m) Y_{J_a}^0(x) from the kinematics mx [n, 2] = (m, cos theta),
+        res = (m_a, Gamma_a) interleaved and the spins J_a."""
+        mx = np.ascontiguousarray(mx, dtype=np.float64).reshape(-1, 2)
+        sp = np.ascontiguousarray(spins, dtype=np.int32)
+        r = np.ascontiguousarray(res, dtype=np.float64).ravel()
+        A = np.empty((mx.shape[0], sp.size), dtype=np.complex128)
+        if self.lib.orc_kin_amplitudes(mx.shape[0], _ptr(mx), sp.size, _ptr(sp), _ptr(r), _ptr(A)):
+            raise ValueError("oracle: invalid arguments")
+        return A
+
+    def kin_nll_grad(self, mx_data, mx_mc, V, res, spins, w=None, n_gen=None, extended=False):
+        """NLL, V gradient [2k] and resonance gradient [2k] = (dNLL/dm_a, dNLL/dGamma_a)
+        with amplitudes from the kinematics (Eq. 2, or Eq. 3 if extended)."""
+        V = _c128(V).ravel()
+        k = V.size
+        sp = np.ascontiguousarray(spins, dtype=np.int32)
+        r = np.ascontiguousarray(res, dtype=np.float64).ravel()
+        md = np.ascontiguousarray(mx_data, dtype=np.float64).reshape(-1, 2)
+        mm = np.ascontiguousarray(mx_mc, dtype=np.float64).reshape(-1, 2)
+        wm = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+        nll = np.zeros(1)
+        gv = np.zeros(2 * k)
+        gr = np.zeros(2 * k)
+        if sp.size != k or r.size != 2 * k or self.lib.orc_kin_nll_grad(
+                md.shape[0], _ptr(md), mm.shape[0], _ptr(mm), _ptr(wm), float(n_gen or 0.0), k, _ptr(sp),
+                _ptr(r), _ptr(V), int(bool(extended)), _ptr(nll), _ptr(gv), _ptr(gr)):
+            raise ValueError("oracle: invalid arguments")
+        return float(nll[0]), gv, gr
 
     def gram(self, A_mc, w=None, n_gen=None) -> np.ndarray:
         """MC integral matrix M_ab = (1/N_gen) sum_j w_j conj(A_ja) A_jb (bracket of Eq. 3)."""
@@ -178,6 +215,14 @@ def nll_grad(A_data, A_mc, V, w=None, n_gen=None, extended=False, parts=False):
 def nll_grad_chunked(A_data, A_mc, V, w=None, n_gen=None, extended=False, threads=0, parts=False):
     return default().nll_grad_chunked(A_data, A_mc, V, w=w, n_gen=n_gen, extended=extended, threads=threads,
                                       parts=parts)
+
+
+def kin_amplitudes(mx, spins, res):
+    return default().kin_amplitudes(mx, spins, res)
+
+
+def kin_nll_grad(mx_data, mx_mc, V, res, spins, w=None, n_gen=None, extended=False):
+    return default().kin_nll_grad(mx_data, mx_mc, V, res, spins, w=w, n_gen=n_gen, extended=extended)
 
 
 def gram(A_mc, w=None, n_gen=None):

@@ -309,6 +309,47 @@ def make_sample(cfg: int, scale: float = 1.0, seed: int = 0, weighted: bool = Fa
     return Sample(waves, A_data, A_mc, w, n_gen, vt)
 
 
+@dataclasses.dataclass
+class KinSample:
+    """Per-event kinematics of a workload: (m_KK, cos theta) as FP32 pairs."""
+    waves: Waves
+    mx_data: np.ndarray        # [N_data, 2] float32
+    mx_mc: np.ndarray          # [N_MC, 2] float32
+    w_mc: Optional[np.ndarray]
+    n_gen: float
+    V_true: np.ndarray
+
+    @property
+    def k(self) -> int:
+        return self.waves.k
+
+    @property
+    def res(self) -> np.ndarray:
+        """(m_a, Gamma_a) interleaved, FP64."""
+        r = np.empty(2 * self.k)
+        r[0::2], r[1::2] = self.waves.mass, self.waves.width
+        return r
+
+
+def make_kin_sample(cfg: int, scale: float = 1.0, seed: int = 0, weighted: bool = False,
+                    n_data: Optional[int] = None, n_mc: Optional[int] = None, k: Optional[int] = None,
+                    fit: int = 0) -> KinSample:
+    """The kinematics make_sample draws (same seeds, same accept-reject of the data
+    at V_true), kept as FP32 (m, cos theta) pairs instead of amplitude rows."""
+    base = CONFIGS.get(cfg, {})
+    nd = int(round((n_data if n_data is not None else base["n_data"]) * (scale if n_data is None else 1)))
+    nm = int(round((n_mc if n_mc is not None else base["n_mc"]) * (scale if n_mc is None else 1)))
+    k = k if k is not None else base["k"]
+    waves = waves_for(cfg, k=k, seed=seed, fit=fit)
+    vt = v_true(cfg, waves.k, seed=seed, fit=fit)
+    m, x, w = mc_kinematics(rng_for(cfg, seed, _S_MC * 1000 + fit), nm, waves, weighted)
+    md, xd = data_kinematics(rng_for(cfg, seed, _S_PILOT * 1000 + fit),
+                             rng_for(cfg, seed, _S_DATA * 1000 + fit), nd, waves, vt)
+    mx_mc = np.stack([m, x], axis=1).astype(np.float32)
+    mx_data = np.stack([md, xd], axis=1).astype(np.float32)
+    return KinSample(waves, mx_data, mx_mc, None if w is None else w.astype(np.float32), float(nm), vt)
+
+
 def multifit_table(nfits: int = 64, seed: int = 0):
     """The uneven multi-fit family: per fit (N_data, K, N_MC = 5 N_data).
 
