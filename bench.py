@@ -122,8 +122,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--extras", default="batched,surrogate,hessian,multifit",
-                    help="comma list of batched, surrogate, hessian, multifit (or none)")
+    ap.add_argument("--extras", default="batched,surrogate,hessian,kinematic,multifit",
+                    help="comma list of batched, surrogate, hessian, kinematic, multifit (or none)")
     ap.add_argument("--probe", action="store_true",
                     help="for HBM counter runs: a few evaluations plus a plain device copy of the "
                          "same byte count (the counter scale reference); prints no JSON")
@@ -231,6 +231,8 @@ def main():
         rec["extras"]["surrogate"] = extra_surrogate(ctx, k)
     ctx.close()
     del s
+    if "kinematic" in extras:
+        rec["extras"]["kinematic"] = extra_kinematic()
     if "batched" in extras:
         rec["extras"]["batched"] = extra_batched()
     if "multifit" in extras:
@@ -422,6 +424,65 @@ def extra_hessian(ctx, V, nd: int, k: int, reps: int = 20):
                          "traffic": None, "kernel": "hess_partial_kernel (FP64) + finish + assembly",
                          "alg_flops_per_call": alg_flops,
                          "note": "wall time of the synchronous call (V upload, kernels, 2K x 2K readback)"}}
+
+
+# Algorithmic FP64 flops of the kinematic evaluation (FMA = 2): per (event, wave)
+# the Breit-Wigner (m_a^2 - m^2, |D|^2, reciprocal with two Newton steps, BW),
+# Y_J^0, A and its share of z: 28; the V-gradient term, conj(u) V_a Y_a, BW^2
+# and the two resonance-gradient terms: 38.  Per event: Legendre polynomials,
+# I, ln I or w I, 1/I and u: 30.
+KIN_FLOPS_PER_EVENT_WAVE = 66
+KIN_FLOPS_PER_EVENT = 30
+
+
+def extra_kinematic(reps: int = 50):
+    """Amplitudes formed on the GPU from (m, cos theta) with floating masses and
+    widths: NLL, V gradient and (m_a, Gamma_a) gradient on the single-V workload's
+    kinematics (K = 16, 1e6 data + 5e6 MC events, 8 bytes per event)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1108_5882_amd import KinContext
+
+    s = synth.make_kin_sample(1)
+    V = synth.eval_vectors(1, 1, s.k)[0]
+    nd, nm, k = s.mx_data.shape[0], s.mx_mc.shape[0], s.k
+    stream = torch.cuda.Stream()
+    kc = KinContext(s.waves.J, stream=stream)
+    kc.set_events("data", s.mx_data)
+    kc.set_events("mc", s.mx_mc)
+    for _ in range(5):
+        kc.nll_grad(V, s.res)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for _ in range(reps):
+        kc.nll_grad(V, s.res)
+    sync_ms = (time.perf_counter() - w0) / reps * 1e3
+    v = np.empty(2 * k)
+    v[0::2], v[1::2] = V.real, V.imag
+    Vd, Rd = torch.from_numpy(v).cuda(), torch.from_numpy(s.res).cuda()
+    out = torch.zeros(4 * k + 2, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        kc.nll_grad_async(Vd, Rd, out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    k_ms = ev0.elapsed_time(ev1) / reps
+    kc.close()
+    events = nd + nm
+    flops = events * (KIN_FLOPS_PER_EVENT + KIN_FLOPS_PER_EVENT_WAVE * k)
+    log(f"kinematic: {sync_ms:.3f} ms per synchronous call, {k_ms:.3f} ms per launch (back to back)")
+    return {"workload": f"NLL + V and (mass, width) gradients with amplitudes formed on the GPU from (m, cos theta), "
+                        f"K={k}, {nd} data + {nm} MC events, FP64 arithmetic",
+            "value": events / (sync_ms * 1e-3), "unit": "event-evals/s", "ms_per_call": sync_ms,
+            "kernel_ms": k_ms,
+            "roofline": {"bound": "alu", "achieved": flops / (k_ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFS,
+                         "unit": "TFLOP/s", "frac": flops / (k_ms * 1e-3) / 1e12 / FP64_PEAK_TFS, "traffic": None,
+                         "kernel": "kin_kernel<L=4> (4 waves per lane)", "alg_flops_per_launch": flops,
+                         "hbm_bytes_per_launch": events * 8}}
 
 
 def extra_multifit(steps: int = 50):

@@ -315,6 +315,61 @@ pwa_status pwa_kernel_time(pwa_ctx *ctx, double *avg_ms, int64_t *count);
 pwa_status pwa_batch_kernel_time(pwa_ctx *ctx, double *avg_ms, int64_t *count);
 
 /* ------------------------------------------------------------------------
+ * Amplitudes formed on the device from each event's kinematics, so that the
+ * masses and widths of the resonances can be fit parameters (Section 2: the
+ * amplitudes can be precomputed only while masses and widths are constant).
+ * Each event is (m, cos theta) in FP32 (8 bytes) and wave a has a spin J_a
+ * (0..4); per evaluation, with resonance parameters (m_a, Gamma_a),
+ *     A_a = BW_a(m) Y_{J_a}^0(cos theta),
+ *     BW_a(m) = 1 / (m_a^2 - m^2 - i m_a Gamma_a)   (fixed-width Breit-Wigner),
+ *     Y_J^0(x) = sqrt((2 J + 1) / (4 pi)) P_J(x)   (Legendre polynomial P_J),
+ * and the NLL of Eq. 2 (or Eq. 3) over these amplitudes, its gradient in V
+ * (as pwa_nll_grad) and its gradient in (m_a, Gamma_a):
+ *     dNLL/dt = -sum_data (1/I) dI/dt + c sum_MC w dI/dt,
+ *     dI/dt = 2 Re(conj(z) V_a Y_a dBW_a/dt),
+ *     dBW_a/dm_a = -(2 m_a - i Gamma_a) BW_a^2,  dBW_a/dGamma_a = i m_a BW_a^2,
+ * c = N_D / (N_gen S) (Eq. 2) or 1 / N_gen (Eq. 3).  Everything after the
+ * FP32 kinematics is FP64; the MC rows are streamed on every evaluation (the
+ * MC bracket changes with the masses and widths).
+ * ------------------------------------------------------------------------ */
+typedef struct pwa_kin pwa_kin;
+
+/* Create a kinematic context for k waves (1..PWA_MAX_K) with spins spin[k]
+ * (each 0..4; PWA_E_UNSUPPORTED otherwise) on `device`; stream as in
+ * pwa_create.  Errors: PWA_E_INVAL, PWA_E_UNSUPPORTED, PWA_E_NOMEM, PWA_E_HIP. */
+pwa_status pwa_kin_create(pwa_kin **out, int device, int32_t k, const int32_t *spin, void *stream);
+pwa_status pwa_kin_destroy(pwa_kin *kc);
+
+/* Store the events of one sample: mx = n pairs (m, cos theta) of FP32, w (MC
+ * only) n FP32 weights or NULL, n_gen as in pwa_set_amplitudes.  `where` as in
+ * pwa_set_amplitudes (PWA_BORROW: device arrays used in place, 8-byte aligned
+ * events, valid until replaced or destroyed).  Errors: PWA_E_INVAL,
+ * PWA_E_NOMEM, PWA_E_HIP. */
+pwa_status pwa_kin_set_events(pwa_kin *kc, pwa_set which, const float *mx, int64_t n, pwa_where where,
+                              const float *w, double n_gen);
+
+/* 0: Eq. 2 form, 1: Eq. 3 form. */
+pwa_status pwa_kin_set_mode(pwa_kin *kc, int extended);
+
+/* NLL at V (host, 2k doubles) and res (host, 2k doubles: m_a, Gamma_a
+ * interleaved, finite and positive); grad_v (2k, as pwa_nll_grad) and
+ * grad_res (2k: dNLL/dm_a, dNLL/dGamma_a interleaved) may be NULL.  One
+ * launch; waits for the result.  Errors: PWA_E_INVAL, PWA_E_STATE,
+ * PWA_E_DOMAIN (NLL = +inf), PWA_E_HIP. */
+pwa_status pwa_kin_nll_grad(pwa_kin *kc, const double *V, const double *res, double *nll, double *grad_v,
+                            double *grad_res);
+
+/* Device-side variant: V_dev and res_dev (2k doubles each) read when the
+ * kernel runs, out_dev (4k + 2 doubles) written as [NLL, grad_v[2k],
+ * grad_res[2k], flags] (flags nonzero: domain failure, NLL = +inf).  No wait,
+ * no allocation.  res_dev must hold positive values (not checked).
+ * Errors (host-side only): PWA_E_INVAL, PWA_E_STATE, PWA_E_HIP. */
+pwa_status pwa_kin_nll_grad_async(pwa_kin *kc, const double *V_dev, const double *res_dev, double *out_dev);
+
+/* Message for the last failing call on this context (or on a NULL context). */
+const char *pwa_kin_last_error(const pwa_kin *kc);
+
+/* ------------------------------------------------------------------------
  * Many independent fits (Section 2: fits are repeated from many starting
  * points and with many models).  Every fit has its own samples and its own
  * production vector; one minimiser iteration of all fits is one persistent

@@ -67,7 +67,7 @@ class Oracle:
         self.has_kin = hasattr(lib, "orc_kin_nll_grad")
         if self.has_kin:
             lib.orc_kin_amplitudes.argtypes = [I64, P, I32, P, P, P]
-            lib.orc_kin_nll_grad.argtypes = [I64, P, I64, P, P, D, I32, P, P, P, ctypes.c_int, P, P, P]
+            lib.orc_kin_nll_grad.argtypes = [I64, P, I64, P, P, D, I32, P, P, P, ctypes.c_int, P, P, P, P]
             fns += [lib.orc_kin_amplitudes, lib.orc_kin_nll_grad]
         for f in fns:
             f.restype = ctypes.c_int
@@ -138,9 +138,10 @@ class Oracle:
             raise ValueError("oracle: invalid arguments")
         return A
 
-    def kin_nll_grad(self, mx_data, mx_mc, V, res, spins, w=None, n_gen=None, extended=False):
+    def kin_nll_grad(self, mx_data, mx_mc, V, res, spins, w=None, n_gen=None, extended=False, parts=False):
         """NLL, V gradient [2k] and resonance gradient [2k] = (dNLL/dm_a, dNLL/dGamma_a)
-        with amplitudes from the kinematics (Eq. 2, or Eq. 3 if extended)."""
+        with amplitudes from the kinematics (Eq. 2, or Eq. 3 if extended); with
+        parts=True also the raw sums (sum_log, s_raw, GD, HM, RD, RM)."""
         V = _c128(V).ravel()
         k = V.size
         sp = np.ascontiguousarray(spins, dtype=np.int32)
@@ -151,10 +152,15 @@ class Oracle:
         nll = np.zeros(1)
         gv = np.zeros(2 * k)
         gr = np.zeros(2 * k)
+        pr = np.zeros(2 + 8 * k)
         if sp.size != k or r.size != 2 * k or self.lib.orc_kin_nll_grad(
                 md.shape[0], _ptr(md), mm.shape[0], _ptr(mm), _ptr(wm), float(n_gen or 0.0), k, _ptr(sp),
-                _ptr(r), _ptr(V), int(bool(extended)), _ptr(nll), _ptr(gv), _ptr(gr)):
+                _ptr(r), _ptr(V), int(bool(extended)), _ptr(nll), _ptr(gv), _ptr(gr), _ptr(pr)):
             raise ValueError("oracle: invalid arguments")
+        if parts:
+            d = dict(sum_log=pr[0], s_raw=pr[1], GD=pr[2:2 + 2 * k].copy(), HM=pr[2 + 2 * k:2 + 4 * k].copy(),
+                     RD=pr[2 + 4 * k:2 + 6 * k].copy(), RM=pr[2 + 6 * k:].copy())
+            return float(nll[0]), gv, gr, d
         return float(nll[0]), gv, gr
 
     def gram(self, A_mc, w=None, n_gen=None) -> np.ndarray:
@@ -221,8 +227,8 @@ def kin_amplitudes(mx, spins, res):
     return default().kin_amplitudes(mx, spins, res)
 
 
-def kin_nll_grad(mx_data, mx_mc, V, res, spins, w=None, n_gen=None, extended=False):
-    return default().kin_nll_grad(mx_data, mx_mc, V, res, spins, w=w, n_gen=n_gen, extended=extended)
+def kin_nll_grad(mx_data, mx_mc, V, res, spins, w=None, n_gen=None, extended=False, parts=False):
+    return default().kin_nll_grad(mx_data, mx_mc, V, res, spins, w=w, n_gen=n_gen, extended=extended, parts=parts)
 
 
 def gram(A_mc, w=None, n_gen=None):

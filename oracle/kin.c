@@ -29,7 +29,9 @@
  * res[2a] = m_a, res[2a+1] = Gamma_a; V and the gradients interleaved (re, im)
  * or (d/dm_a, d/dGamma_a).  Every function returns 0, or -1 on invalid
  * arguments.  NLL is +inf when some data intensity is not positive or (Eq. 2
- * form) S is not positive.
+ * form) S is not positive.  `parts` (optional, 2 + 8k doubles) receives the
+ * raw sums: sum ln I, sum w I, G, H (the V-gradient sums of data and MC) and
+ * R_data, R_MC (the resonance-gradient sums).
  */
 #include <complex.h>
 #include <math.h>
@@ -144,7 +146,7 @@ static int kin_sums(int64_t n, const double *mx, const double *w, int32_t k, con
 
 int orc_kin_nll_grad(int64_t nd, const double *mx_d, int64_t nm, const double *mx_m, const double *w,
                      double n_gen, int32_t k, const int32_t *spin, const double *res, const double *Vri,
-                     int extended, double *nll, double *grad_v, double *grad_res) {
+                     int extended, double *nll, double *grad_v, double *grad_res, double *parts) {
     if (nd < 0 || nm < 0 || !Vri || !nll || !valid(k, spin, res)) return -1;
     if ((nd > 0 && !mx_d) || (nm > 0 && !mx_m)) return -1;
     if (nd > 0 && nm == 0) return -1;
@@ -172,6 +174,11 @@ int orc_kin_nll_grad(int64_t nd, const double *mx_d, int64_t nm, const double *m
     for (int32_t i = 0; i < 2 * k; ++i) {
         if (grad_v) grad_v[i] = 2.0 * (-GD[i] + c * HM[i]);
         if (grad_res) grad_res[i] = -RD[i] + c * RM[i];
+    }
+    if (parts) {   /* raw sums: sum ln I, sum w I, then G, H, R_data, R_MC (2k each) */
+        parts[0] = sum_log;
+        parts[1] = s_raw;
+        for (int32_t i = 0; i < 8 * k; ++i) parts[2 + i] = buf[i];
     }
     free(buf);
     free(V);

@@ -8,8 +8,8 @@ kernels (csrc/); this package is the ctypes binding.  Importing the package
 does not load the library; creating a Context does, and raises if it is
 missing.
 """
-from ._lib import (Context, DomainError, Mlp, MultiFit, PwaError, EXPORTS, LIB_PATH, load,  # noqa: F401
+from ._lib import (Context, DomainError, KinContext, Mlp, MultiFit, PwaError, EXPORTS, LIB_PATH, load,  # noqa: F401
                    nll_grad_noalloc)
 
-__all__ = ["Context", "DomainError", "Mlp", "MultiFit", "PwaError", "EXPORTS", "LIB_PATH", "load",
+__all__ = ["Context", "DomainError", "KinContext", "Mlp", "MultiFit", "PwaError", "EXPORTS", "LIB_PATH", "load",
            "nll_grad_noalloc"]

@@ -34,6 +34,8 @@ EXPORTS = [
     "pwa_mlp_param_count", "pwa_mlp_create", "pwa_mlp_destroy", "pwa_mlp_set_params", "pwa_mlp_get_params",
     "pwa_mlp_features", "pwa_mlp_targets", "pwa_mlp_predict", "pwa_mlp_loss_grad", "pwa_mlp_train",
     "pwa_mlp_select", "pwa_mlp_last_error", "pwa_nll_grad_noalloc",
+    "pwa_kin_create", "pwa_kin_destroy", "pwa_kin_set_events", "pwa_kin_set_mode", "pwa_kin_nll_grad",
+    "pwa_kin_nll_grad_async", "pwa_kin_last_error",
 ]
 
 
@@ -135,6 +137,12 @@ def load(path: str = LIB_PATH):
         "pwa_mlp_train": [P, P, P, I64, P, I32, I32, ctypes.c_float, P, ctypes.POINTER(D)],
         "pwa_mlp_select": [P, P, I64, I32, P],
         "pwa_nll_grad_noalloc": [ctypes.c_int, P, I64, P, I64, P, D, I32, I64, ctypes.c_int, P, P, P],
+        "pwa_kin_create": [ctypes.POINTER(P), ctypes.c_int, I32, P, P],
+        "pwa_kin_destroy": [P],
+        "pwa_kin_set_events": [P, ctypes.c_int, P, I64, ctypes.c_int, P, D],
+        "pwa_kin_set_mode": [P, ctypes.c_int],
+        "pwa_kin_nll_grad": [P, P, P, P, P, P],
+        "pwa_kin_nll_grad_async": [P, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -144,6 +152,8 @@ def load(path: str = LIB_PATH):
     lib.pwa_last_error.restype = ctypes.c_char_p
     lib.pwa_multi_last_error.argtypes = [P]
     lib.pwa_multi_last_error.restype = ctypes.c_char_p
+    lib.pwa_kin_last_error.argtypes = [P]
+    lib.pwa_kin_last_error.restype = ctypes.c_char_p
     lib.pwa_mlp_last_error.argtypes = [P]
     lib.pwa_mlp_last_error.restype = ctypes.c_char_p
     lib.pwa_mlp_param_count.argtypes = [I32, I32]
@@ -497,6 +507,120 @@ class Context:
         n = ctypes.c_int64()
         self._check(self.lib.pwa_batch_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+class KinContext:
+    """Likelihood with amplitudes formed on the GPU from each event's kinematics
+    (pwa_kin): resonance masses and widths are parameters next to V.
+
+    spins: the J of each wave (0..4).  Events: (m, cos theta) pairs [n, 2].
+    """
+
+    def __init__(self, spins, device: int = 0, stream=None):
+        self.lib = load()
+        self.device = int(device)
+        sp = np.ascontiguousarray(spins, dtype=np.int32)
+        self.k = int(sp.size)
+        self._stream_obj = stream
+        self._borrowed = {}
+        h = ctypes.c_void_p()
+        s = _stream_handle(stream)
+        self._check(self.lib.pwa_kin_create(ctypes.byref(h), device, self.k, _ptr(sp),
+                                            None if s is None else ctypes.c_void_p(s)), None)
+        self.h = h
+        self._buf = np.zeros(4 * self.k + 1)
+        self._in = np.zeros(4 * self.k)
+
+    def _check(self, status: int, h=-1):
+        if status == OK:
+            return
+        msg = self.lib.pwa_kin_last_error(self.h if h == -1 else h)
+        msg = msg.decode() if msg else ""
+        raise (DomainError if status == E_DOMAIN else PwaError)(status, msg)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.pwa_kin_destroy(self.h)
+            self.h = ctypes.c_void_p()
+        self._borrowed = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_events(self, which: str, mx, w=None, n_gen: Optional[float] = None, borrow: bool = False):
+        """mx: [n, 2] float32 (m, cos theta) as numpy (host) or a GPU tensor (copied, or
+        used in place with borrow=True); w: matching float32 weights or None."""
+        wh = {"data": DATA, "mc": MC}[which]
+        if _is_torch(mx) and mx.is_cuda:
+            import torch
+            for t, name in ((mx, "mx"),) + (((w, "w"),) if w is not None else ()):
+                if not _is_torch(t) or t.device.index != self.device or t.dtype != torch.float32 \
+                        or not t.is_contiguous():
+                    raise TypeError(f"{name} must be a contiguous float32 tensor on cuda:{self.device}")
+            if mx.dim() != 2 or mx.shape[1] != 2 or (w is not None and w.numel() != mx.shape[0]):
+                raise ValueError("mx must be [n, 2] and w [n]")
+            self._check(self.lib.pwa_kin_set_events(self.h, wh, ctypes.c_void_p(mx.data_ptr()), mx.shape[0],
+                                                    BORROW if borrow else DEVICE,
+                                                    None if w is None else ctypes.c_void_p(w.data_ptr()),
+                                                    float(n_gen or 0.0)))
+            if borrow:
+                self._borrowed[which] = (mx, w)
+            else:
+                self._borrowed.pop(which, None)
+            return
+        if borrow:
+            raise TypeError("only a GPU tensor can be borrowed")
+        mx = np.ascontiguousarray(mx.cpu().numpy() if _is_torch(mx) else mx, dtype=np.float32)
+        if mx.ndim != 2 or mx.shape[1] != 2:
+            raise ValueError("mx must be [n, 2]")
+        wa = None if w is None else np.ascontiguousarray(w, dtype=np.float32)
+        if wa is not None and wa.shape != (mx.shape[0],):
+            raise ValueError("w must be [n]")
+        self._check(self.lib.pwa_kin_set_events(self.h, wh, _ptr(mx), mx.shape[0], HOST, _ptr(wa),
+                                                float(n_gen or 0.0)))
+        self._borrowed.pop(which, None)
+
+    def set_mode(self, extended: bool = False):
+        self._check(self.lib.pwa_kin_set_mode(self.h, int(bool(extended))))
+
+    def nll_grad(self, V, res):
+        """(NLL, gradient in V [2k] (Re, Im interleaved), gradient in res [2k]
+        (d/dm_a, d/dGamma_a interleaved)) at V ([k] complex or [2k] real) and
+        res = (m_a, Gamma_a) interleaved [2k]."""
+        V = np.asarray(V)
+        k = self.k
+        if np.iscomplexobj(V):
+            self._in[0:2 * k:2], self._in[1:2 * k:2] = V.real, V.imag
+        else:
+            self._in[:2 * k] = np.asarray(V, dtype=np.float64).ravel()
+        self._in[2 * k:] = np.asarray(res, dtype=np.float64).ravel()
+        b = self._buf.ctypes.data
+        self._check(self.lib.pwa_kin_nll_grad(self.h, self._in.ctypes.data, self._in.ctypes.data + 16 * k, b,
+                                              b + 8, b + 8 + 16 * k))
+        return float(self._buf[0]), self._buf[1:1 + 2 * k].copy(), self._buf[1 + 2 * k:].copy()
+
+    def nll_grad_async(self, V_dev, res_dev, out_dev):
+        """V_dev, res_dev: float64 GPU tensors [2k]; out_dev float64 [4k + 2]
+        (nll, grad_v[2k], grad_res[2k], flags); enqueued on the context's stream."""
+        import torch
+        for t, name, nv in ((V_dev, "V_dev", 2 * self.k), (res_dev, "res_dev", 2 * self.k),
+                            (out_dev, "out_dev", 4 * self.k + 2)):
+            if not _is_torch(t) or not t.is_cuda or t.device.index != self.device or t.dtype != torch.float64:
+                raise TypeError(f"{name} must be a float64 tensor on cuda:{self.device}")
+            if t.numel() != nv or not t.is_contiguous():
+                raise ValueError(f"{name} must be contiguous with {nv} elements")
+        self._check(self.lib.pwa_kin_nll_grad_async(self.h, ctypes.c_void_p(V_dev.data_ptr()),
+                                                    ctypes.c_void_p(res_dev.data_ptr()),
+                                                    ctypes.c_void_p(out_dev.data_ptr())))
 
 
 class MultiFit:

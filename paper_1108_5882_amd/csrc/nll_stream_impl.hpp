@@ -33,6 +33,7 @@
 #include <cmath>
 #include <type_traits>
 
+#include "block_reduce.hpp"
 #include "internal.hpp"
 
 namespace pwa {
@@ -149,102 +150,17 @@ struct EventMath<double> {
 };
 
 // ------------------------------------------- combine of the block partials
-// Partials and group sums cross blocks, and so the XCDs' separate L2 caches.
-// They are stored and loaded as device-scope atomics (written through to, and
-// read from, the device's coherence point), and each block waits for its own
-// stores to complete before the arrival count that announces them.  A
-// device-scope fence would order plain stores too, but on gfx950 it writes
-// back and invalidates the whole L2 of the block's XCD, which costs far more
-// than the pass over the rows when every block pays it.
-__device__ __forceinline__ void st_dev(double *p, double v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double ld_dev(const double *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-// the result may go to host memory: written through at system scope
-__device__ __forceinline__ void st_sys(double *p, double v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-// every memory operation this wave issued has completed
-__device__ __forceinline__ void wait_stores() { __builtin_amdgcn_s_waitcnt(0); }
-
 // Called by every block after it stored its partial with st_dev (PS doubles:
 // the summed log term or w I, then the complex adjoint sums).  The last block
-// of each group adds the group's partials; the last group adds the group sums
-// and writes the result.
+// of the launch forms NLL and gradient from the totals.
 template <int PS, int NT>
 __device__ __forceinline__ void finish(const StreamArgs &p, double log_scale) {
-    __shared__ unsigned s_last;
     __shared__ double tot[2 * PS];
     __shared__ double mv[PS];
     __shared__ double s_c;
     const int tid = threadIdx.x;
-    const int nbt = p.nb[0] + p.nb[1];
-    const int grp = (int)blockIdx.x / kFinishGroup;
-    const int g0 = grp * kFinishGroup;
-    const int gn = min(kFinishGroup, nbt - g0);
-    const int ngroups = (nbt + kFinishGroup - 1) / kFinishGroup;
-
-    wait_stores();
-    __syncthreads();
-    if (tid == 0) s_last = atomicAdd(&p.counters[1 + grp], 1u) == (unsigned)(gn - 1);
-    __syncthreads();
-    if (!s_last) return;
-
-    // group sums: data columns then MC columns, blocks in order (all loads of a
-    // column in flight at once; blocks outside the group or the segment add 0)
-    for (int col = tid; col < 2 * PS; col += NT) {
-        const int sg = col >= PS ? 1 : 0;
-        const int c = col - sg * PS;
-        double v[kFinishGroup];
-#pragma unroll
-        for (int i = 0; i < kFinishGroup; ++i)
-            v[i] = ld_dev(p.partials + (int64_t)(g0 + (i < gn ? i : gn - 1)) * PS + c);
-        double s = 0.0;
-#pragma unroll
-        for (int i = 0; i < kFinishGroup; ++i) {
-            const bool take = i < gn && ((g0 + i >= p.nb[0]) == (sg == 1));
-            s += take ? v[i] : 0.0;
-        }
-        st_dev(p.gsums + (int64_t)grp * 2 * PS + col, s);
-    }
-    if (tid == 0) __hip_atomic_store(&p.counters[1 + grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    wait_stores();
-    __syncthreads();
-    if (tid == 0) s_last = atomicAdd(&p.counters[0], 1u) == (unsigned)(ngroups - 1);
-    __syncthreads();
-    if (!s_last) return;
-
-    // totals over the groups: TPC threads per column, thread r adding groups
-    // r, r + TPC, ... in order (16 loads in flight), then the TPC sums of a
-    // column in thread order
-    constexpr int NCOL = 2 * PS;
-    constexpr int TPC = NT / NCOL > 0 ? NT / NCOL : 1;
-    __shared__ double part[NCOL * TPC];
-    for (int slot = tid; slot < NCOL * TPC; slot += NT) {
-        const int col = slot / TPC, r = slot % TPC;
-        double s = 0.0;
-        for (int gb = r; gb < ngroups; gb += 16 * TPC) {
-            double v[16];
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int gi = gb + u * TPC;
-                v[u] = ld_dev(p.gsums + (int64_t)(gi < ngroups ? gi : ngroups - 1) * NCOL + col);
-            }
-#pragma unroll
-            for (int u = 0; u < 16; ++u) s += gb + u * TPC < ngroups ? v[u] : 0.0;
-        }
-        part[slot] = s;
-    }
-    if (tid == 0) __hip_atomic_store(&p.counters[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    for (int col = tid; col < NCOL; col += NT) {
-        double s = 0.0;
-        for (int r = 0; r < TPC; ++r) s += part[col * TPC + r];
-        tot[col] = s;
-    }
-    __syncthreads();
+    if (!reduce_blocks<PS, NT>(ReduceBufs{p.partials, p.gsums, p.counters, p.nb[0], p.nb[0] + p.nb[1]}, tot))
+        return;
 
     // Eq. 2 form:  NLL = -sum ln I + N_D ln S,   c = N_D / (N_gen S)
     // Eq. 3 form:  NLL = -sum ln I + S,          c = 1 / N_gen

@@ -91,3 +91,20 @@ def test_binding_rejects_host_tensors_for_device_arguments():
     vp, op = c._stage_v(__import__("numpy").arange(4) * (1 + 1j))
     assert list(c._vbuf) == [0, 0, 1, 1, 2, 2, 3, 3] and vp and op
     assert _lib.BORROW == 2
+
+
+def test_kinematic_context_host_checks():
+    """Argument checks of the kinematic context that need no device."""
+    if not os.path.exists(pwa.LIB_PATH):
+        pytest.skip("libpwa.so not built")
+    import ctypes
+    import numpy as np
+    lib = pwa.load()
+    sp = np.array([0, 2, 5], dtype=np.int32)
+    h = ctypes.c_void_p()
+    assert lib.pwa_kin_create(None, 0, 3, sp.ctypes.data, None) == 1
+    assert lib.pwa_kin_create(ctypes.byref(h), 0, 3, sp.ctypes.data, None) == 6     # spin 5 not supported
+    assert b"spin" in lib.pwa_kin_last_error(None)
+    assert lib.pwa_kin_create(ctypes.byref(h), 0, 0, sp.ctypes.data, None) == 1
+    assert lib.pwa_kin_destroy(None) == 0
+    assert lib.pwa_kin_set_mode(None, 0) == 1
