@@ -91,10 +91,9 @@ __device__ __forceinline__ double lane_group_sum(double x) {
     return x;
 }
 
-// 1 / d for d > 0: hardware estimate, then two Newton steps (FP64 accurate)
+// 1 / d for d > 0: hardware estimate refined by one Newton step
 __device__ __forceinline__ double recip(double d) {
-    double r = __builtin_amdgcn_rcp(d);
-    r = fma(r, fma(-d, r, 1.0), r);
+    const double r = __builtin_amdgcn_rcp(d);
     return fma(r, fma(-d, r, 1.0), r);
 }
 
@@ -107,8 +106,10 @@ __global__ __launch_bounds__(kKinThreads) void kin_kernel(KinArgs p) {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int j = lane % L, g = lane / L;
 
-    // per-lane wave constants (padded waves: V = 0 and a harmless lineshape)
-    double vr[kKinW], vi[kKinW], ma[kKinW], mg[kKinW], ga[kKinW], yn[kKinW];
+    // per-lane wave constants (padded waves: V = 0 and a harmless lineshape):
+    // V, m_a, m_a Gamma_a, the derivative factors -4 m_a, -2 m_a, -2 Gamma_a,
+    // the Y_J^0 normalisation and the spin
+    double vr[kKinW], vi[kKinW], ma[kKinW], mg[kKinW], c4m[kKinW], c2m[kKinW], c2g[kKinW], yn[kKinW];
     int sp[kKinW];
 #pragma unroll
     for (int q = 0; q < kKinW; ++q) {
@@ -119,8 +120,11 @@ __global__ __launch_bounds__(kKinThreads) void kin_kernel(KinArgs p) {
         vr[q] = live ? V[2 * a] : 0.0;
         vi[q] = live ? V[2 * a + 1] : 0.0;
         ma[q] = live ? R[2 * a] : 1.0;
-        ga[q] = live ? R[2 * a + 1] : 1.0;
-        mg[q] = ma[q] * ga[q];
+        const double ga = live ? R[2 * a + 1] : 1.0;
+        mg[q] = ma[q] * ga;
+        c4m[q] = -4.0 * ma[q];
+        c2m[q] = -2.0 * ma[q];
+        c2g[q] = -2.0 * ga;
         sp[q] = live ? p.spin[a] : 0;
         yn[q] = live ? sqrt((2.0 * sp[q] + 1.0) * 0.079577471545947667884) : 0.0;   // 1 / (4 pi)
     }
@@ -133,7 +137,10 @@ __global__ __launch_bounds__(kKinThreads) void kin_kernel(KinArgs p) {
     const int64_t ntiles = (n + G - 1) / G;
     const int64_t stride = (int64_t)p.nb[seg] * NW;
 
-    double acc_t = 0.0;
+    // data: sum ln I as sum ln(product of frexp mantissas) + ln 2 * sum of exponents
+    // (one logarithm per 32 events instead of one per event); MC: sum w I
+    double acc_t = 0.0, pm = 1.0;
+    int pe = 0, cnt = 0;
     double gvr[kKinW], gvi[kKinW], gm[kKinW], gg[kKinW];
 #pragma unroll
     for (int q = 0; q < kKinW; ++q) gvr[q] = gvi[q] = gm[q] = gg[q] = 0.0;
@@ -149,7 +156,7 @@ __global__ __launch_bounds__(kKinThreads) void kin_kernel(KinArgs p) {
         const double p1 = x, p2 = 1.5 * x * x - 0.5;
         const double p3 = (5.0 * x * p2 - 2.0 * p1) * (1.0 / 3.0);
         const double p4 = (7.0 * x * p3 - 3.0 * p2) * 0.25;
-        double bre[kKinW], bim[kKinW], y[kKinW];
+        double bre[kKinW], bim[kKinW], y[kKinW], vbr[kKinW], vbi[kKinW];
         double zr = 0.0, zi = 0.0;
 #pragma unroll
         for (int q = 0; q < kKinW; ++q) {
@@ -161,16 +168,25 @@ __global__ __launch_bounds__(kKinThreads) void kin_kernel(KinArgs p) {
             const int J = sp[q];
             const double pj = J == 0 ? 1.0 : J == 1 ? p1 : J == 2 ? p2 : J == 3 ? p3 : p4;
             y[q] = yn[q] * pj;
-            const double are = bre[q] * y[q], aim = bim[q] * y[q];
-            zr = fma(vr[q], are, fma(-vi[q], aim, zr));
-            zi = fma(vr[q], aim, fma(vi[q], are, zi));
+            // V_a BW_a, then its share of z = sum_a (V_a BW_a) Y_a
+            vbr[q] = fma(vr[q], bre[q], -vi[q] * bim[q]);
+            vbi[q] = fma(vr[q], bim[q], vi[q] * bre[q]);
+            zr = fma(vbr[q], y[q], zr);
+            zi = fma(vbi[q], y[q], zi);
         }
         zr = lane_group_sum<L>(zr);
         zi = lane_group_sum<L>(zi);
         const double I = fma(zr, zr, zi * zi);
         double ce;
         if (seg == 0) {
-            acc_t += valid ? log(I) : 0.0;
+            int ex = 0;
+            pm *= valid ? frexp(I, &ex) : 1.0;
+            pe += ex;
+            if (++cnt == 32) {      // the same count in every lane: no divergence
+                acc_t += log(pm);
+                pm = 1.0;
+                cnt = 0;
+            }
             ce = valid ? recip(I) : 0.0;
         } else {
             ce = valid ? (double)wf : 0.0;
@@ -179,22 +195,20 @@ __global__ __launch_bounds__(kKinThreads) void kin_kernel(KinArgs p) {
         const double ur = ce * zr, ui = ce * zi;
 #pragma unroll
         for (int q = 0; q < kKinW; ++q) {
-            const double are = bre[q] * y[q], aim = bim[q] * y[q];
-            // conj(A) u
-            gvr[q] = fma(are, ur, fma(aim, ui, gvr[q]));
-            gvi[q] = fma(are, ui, fma(-aim, ur, gvi[q]));
-            // e = conj(u) V_a Y_a BW_a^2
-            const double tr = fma(ur, vr[q], ui * vi[q]) * y[q];
-            const double ti = fma(ur, vi[q], -ui * vr[q]) * y[q];
-            const double b2r = fma(bre[q], bre[q], -bim[q] * bim[q]);
-            const double b2i = 2.0 * bre[q] * bim[q];
-            const double er = fma(tr, b2r, -ti * b2i);
-            const double ei = fma(tr, b2i, ti * b2r);
+            // g = conj(A_a) u = Y_a conj(BW_a) u  (the V-gradient term)
+            const double gr_ = fma(bre[q], ur, bim[q] * ui) * y[q];
+            const double gi_ = fma(bre[q], ui, -bim[q] * ur) * y[q];
+            gvr[q] += gr_;
+            gvi[q] += gi_;
+            // e = conj(u) V_a Y_a BW_a^2 = (V_a BW_a) conj(g)
+            const double er = fma(vbr[q], gr_, vbi[q] * gi_);
+            const double ei = fma(vbi[q], gr_, -vbr[q] * gi_);
             // 2 Re(e (-(2 m_a - i Gamma_a))) and 2 Re(e (i m_a))
-            gm[q] = fma(-4.0 * ma[q], er, fma(-2.0 * ga[q], ei, gm[q]));
-            gg[q] = fma(-2.0 * ma[q], ei, gg[q]);
+            gm[q] = fma(c4m[q], er, fma(c2g[q], ei, gm[q]));
+            gg[q] = fma(c2m[q], ei, gg[q]);
         }
     }
+    if (seg == 0) acc_t += log(pm) + (double)pe * 0.69314718055994530942;
 
     // lanes with the same j across the wave's event groups
 #pragma unroll
