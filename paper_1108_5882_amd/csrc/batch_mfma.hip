@@ -13,6 +13,11 @@
 // leaves registers: the forward's output layout is the adjoint's A operand
 // once the adjoint's event order is permuted the same way in both operands.
 //
+// Operand planes: the split amplitudes do not depend on V, so they are formed
+// once per sample (batch_planes_kernel) in the order and layout the tile's LDS
+// buffers take them, 32-event tiles one after another; per tile a block
+// copies them to LDS with 16-byte loads and stores and no conversion.
+//
 // Arithmetic (split): the forward uses two-term FP16 splits (hi + lo) of the
 // amplitudes, scaled by a power of two per wave, and of W, scaled by a power
 // of two per column: products hi*hi + hi*lo + lo*hi, 22-bit operands.  The
@@ -88,8 +93,8 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
     constexpr int K2 = BatchSmem<KS, CT>::K2;
     constexpr int RS16 = BatchSmem<KS, CT>::RS16;
     constexpr int RST = BatchSmem<KS, CT>::RST;
-    constexpr int kPairs = kTile * K2 / 2;      // float pairs of a tile
-    constexpr int kPer = (kPairs + kThreads - 1) / kThreads;
+    constexpr int kChunks = 16 * K2;            // 16-byte chunks of a tile's four planes
+    constexpr int kPer = (kChunks + kThreads - 1) / kThreads;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int q = lane >> 4, r16 = lane & 15;
@@ -145,19 +150,19 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
     for (int g = 0; g < CT / 2; ++g) tsum[g] = 0.0;
 
     const int nreal = 2 * p.k;                      // real columns present in a row
-    // The next tile's rows are loaded into registers while the current tile is
-    // computed; each thread holds kPer (re, im) pairs and one MC weight.
-    f2 xr[kPer];
+    // The next tile's operand planes are loaded into registers while the current
+    // tile is computed; each thread holds kPer 16-byte chunks and one MC weight.
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    const u4 *planes = static_cast<const u4 *>(p.planes[SEG]);
+    u4 xr[kPer];
     float wr = 0.f;
     auto load_tile = [&](int64_t t) {
 #pragma unroll
         for (int i = 0; i < kPer; ++i) {
             const int c = tid + i * kThreads;
-            xr[i] = f2{0.f, 0.f};
-            if (c < kPairs) {
-                const int e = c / (K2 / 2), r = 2 * (c % (K2 / 2));
-                const int64_t row = t * kTile + e;
-                if (row < n && r < nreal) xr[i] = *reinterpret_cast<const f2 *>(A + 2 * (row * p.ld) + r);
+            if (c < kChunks) {
+                typedef const u4 __attribute__((address_space(1))) *gptr;
+                xr[i] = __builtin_nontemporal_load((gptr)(planes + t * kChunks + c));
             }
         }
         if ((SEG || kRef) && tid < kTile) {
@@ -224,29 +229,25 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
         }
     };
 
-    // stage a tile from the registers into buffer b: FP16 (scaled) row-major
-    // planes and BF16 transposed planes; in the transposed planes event e sits
-    // at position 8 ((e mod 16) / 4) + (e mod 4) + 4 (e / 16), the adjoint's
-    // operand order, so that a lane reads its 8 values in one 16-byte access
+    // stage a tile from the registers into buffer b: plane 0 / 1 are the FP16 hi /
+    // lo row-major planes (K2 halfs per event), plane 2 / 3 the BF16 hi / lo
+    // transposed planes (32 events per real column, in the adjoint's operand
+    // order); each 16-byte chunk goes to its place in the padded LDS rows
     auto stage = [&](BatchSmem<KS, CT> &b) {
 #pragma unroll
         for (int i = 0; i < kPer; ++i) {
             const int c = tid + i * kThreads;
-            if (c < kPairs) {
-                const int e = c / (K2 / 2), r = 2 * (c % (K2 / 2));
-                const float x0 = xr[i][0], x1 = xr[i][1];
-                const float y0 = x0 * p.ascale[r], y1 = x1 * p.ascale[r + 1];
-                const _Float16 h0 = (_Float16)y0, h1 = (_Float16)y1;
-                b.ah[e * RS16 + r] = h0;
-                b.ah[e * RS16 + r + 1] = h1;
-                b.al[e * RS16 + r] = (_Float16)(y0 - (float)h0);
-                b.al[e * RS16 + r + 1] = (_Float16)(y1 - (float)h1);
-                const int pe = 8 * ((e & 15) >> 2) + (e & 3) + 4 * (e >> 4);
-                const __bf16 g0 = (__bf16)x0, g1 = (__bf16)x1;
-                b.bh[r * RST + pe] = g0;
-                b.bh[(r + 1) * RST + pe] = g1;
-                b.bl[r * RST + pe] = (__bf16)(x0 - (float)g0);
-                b.bl[(r + 1) * RST + pe] = (__bf16)(x1 - (float)g1);
+            if (c < kChunks) {
+                const int plane = c / (4 * K2), u = 8 * (c % (4 * K2));
+                u4 *dst;
+                if (plane < 2) {
+                    const int e = u / K2, r = u % K2;
+                    dst = reinterpret_cast<u4 *>((plane == 0 ? b.ah : b.al) + e * RS16 + r);
+                } else {
+                    const int rr = u / kTile, pos = u % kTile;
+                    dst = reinterpret_cast<u4 *>((plane == 2 ? b.bh : b.bl) + rr * RST + pos);
+                }
+                *dst = xr[i];
             }
         }
         if ((SEG || kRef) && tid < kTile) b.wts[tid] = wr;
@@ -513,6 +514,48 @@ __global__ __launch_bounds__(kThreads) void batch_refine_kernel(BatchArgs p) {
                 }
             }
         }
+    }
+}
+
+// Operand planes of one sample, tile after tile (4 planes x 32 x K2 values of 2
+// bytes per tile): FP16 hi / lo of the amplitudes scaled by the power of two
+// of their wave (event-major rows), then BF16 hi / lo of the unscaled
+// amplitudes transposed (real-column-major, event e at position
+// 8 ((e mod 16) / 4) + (e mod 4) + 4 (e / 16)).  Rows past n and columns past
+// 2k hold zeros.  One thread per (event, pair of real columns).
+__global__ void batch_planes_kernel(const float *A, int64_t n, int64_t ld, int nreal, int K2, int64_t ntiles,
+                                    const float *ascale, unsigned short *out) {
+    const int64_t total = ntiles * kTile * (K2 / 2);
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t eg = idx / (K2 / 2);
+        const int r = 2 * (int)(idx % (K2 / 2));
+        const int64_t t = eg / kTile;
+        const int e = (int)(eg % kTile);
+        float x0 = 0.f, x1 = 0.f;
+        if (eg < n && r < nreal) {
+            x0 = A[2 * eg * ld + r];
+            x1 = A[2 * eg * ld + r + 1];
+        }
+        unsigned short *base = out + t * (128 * (int64_t)K2);
+        const float y0 = x0 * ascale[r], y1 = x1 * ascale[r + 1];
+        const _Float16 h0 = (_Float16)y0, h1 = (_Float16)y1;
+        const _Float16 l0 = (_Float16)(y0 - (float)h0), l1 = (_Float16)(y1 - (float)h1);
+        const int pe = 8 * ((e & 15) >> 2) + (e & 3) + 4 * (e >> 4);
+        const __bf16 g0 = (__bf16)x0, g1 = (__bf16)x1;
+        const __bf16 m0 = (__bf16)(x0 - (float)g0), m1 = (__bf16)(x1 - (float)g1);
+        _Float16 *ah = reinterpret_cast<_Float16 *>(base);
+        _Float16 *al = ah + kTile * K2;
+        __bf16 *bh = reinterpret_cast<__bf16 *>(base + 2 * kTile * K2);
+        __bf16 *bl = bh + kTile * K2;
+        ah[e * K2 + r] = h0;
+        ah[e * K2 + r + 1] = h1;
+        al[e * K2 + r] = l0;
+        al[e * K2 + r + 1] = l1;
+        bh[r * kTile + pe] = g0;
+        bh[(r + 1) * kTile + pe] = g1;
+        bl[r * kTile + pe] = m0;
+        bl[(r + 1) * kTile + pe] = m1;
     }
 }
 
@@ -831,6 +874,23 @@ size_t batch_flag_words(int64_t n0, int nv, int k) {
     const int64_t tiles = (n0 + kTile - 1) / kTile;
     const int gpad = (batch_vector_groups(nv, k) + kWaves - 1) / kWaves * kWaves;
     return (size_t)tiles * gpad * 8 * (batch_ct(k) / 2);
+}
+
+size_t batch_plane_bytes(int64_t n, int k) {
+    const int64_t ntiles = (n + kTile - 1) / kTile;
+    return (size_t)ntiles * 256 * (size_t)(32 * batch_ks(k));
+}
+
+hipError_t launch_batch_planes(const float *A, int64_t n, int64_t ld, int k, const float *ascale, void *out,
+                               hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const int K2 = 32 * batch_ks(k);
+    const int64_t ntiles = (n + kTile - 1) / kTile;
+    const int64_t total = ntiles * kTile * (K2 / 2);
+    const int blocks = (int)std::min<int64_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(batch_planes_kernel, dim3(blocks), dim3(256), 0, stream, A, n, ld, 2 * k, K2, ntiles, ascale,
+                       static_cast<unsigned short *>(out));
+    return hipGetLastError();
 }
 
 hipError_t launch_rownorm(const float *A, int64_t n, int64_t ld, int k, float *out, hipStream_t stream) {

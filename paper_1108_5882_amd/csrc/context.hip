@@ -90,6 +90,10 @@ struct pwa_ctx {
     unsigned *b_amax = nullptr;
     // exact refinement of small coherent sums: |A_i|^2 of the data rows, flag words
     bool rnorm_valid = false;
+    // split operand planes of each sample for the batched pass (built from A and ascale)
+    void *b_planes[2] = {nullptr, nullptr};
+    size_t planes_cap[2] = {0, 0};
+    bool planes_valid[2] = {false, false};
     float *b_rnorm = nullptr;
     void *b_flags = nullptr;
     size_t flags_cap = 0;
@@ -365,6 +369,7 @@ pwa_status ensure_amax(pwa_ctx *ctx) {
     }
     ctx->amax_valid = true;
     ctx->ascale_dev_valid = false;
+    ctx->planes_valid[0] = ctx->planes_valid[1] = false;
     return PWA_OK;
 }
 
@@ -432,6 +437,22 @@ pwa_status batch_setup(pwa_ctx *ctx, int32_t nv, BatchArgs &a, int *gpad, bool a
                                     ctx->stream), "hipMemcpyAsync(scales)");
         PWA_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
         ctx->ascale_dev_valid = true;
+    }
+    // operand planes of the streamed samples (built once per sample and scale)
+    for (int sg = 0; sg < 2; ++sg) {
+        if (a.n[sg] == 0) continue;
+        if (!ctx->planes_valid[sg]) {
+            if (!alloc)
+                return fail(ctx, PWA_E_STATE, "batched operand planes not prepared: call pwa_nll_batch once first");
+            if ((st = grow(ctx, &ctx->b_planes[sg], &ctx->planes_cap[sg], batch_plane_bytes(a.n[sg], k),
+                           "hipMalloc(operand planes)")))
+                return st;
+            PWA_HIP(ctx, launch_batch_planes(a.A[sg], a.n[sg], a.ld, k, static_cast<const float *>(ctx->b_ascale),
+                                             ctx->b_planes[sg], ctx->stream),
+                    "operand plane launch");
+            ctx->planes_valid[sg] = true;
+        }
+        a.planes[sg] = ctx->b_planes[sg];
     }
     a.ngroups_pad = *gpad;
     // c^2 of the flag test: sqrt(k) / N_D, at most 1/64.  An unflagged event's
@@ -766,7 +787,8 @@ pwa_status pwa_destroy(pwa_ctx *ctx) {
     if (ctx->counters) (void)hipFree(ctx->counters);
     if (ctx->gram) (void)hipFree(ctx->gram);
     for (void *b : {ctx->b_wfrag, ctx->b_ascale, ctx->b_vscale, ctx->b_V, ctx->b_partials, ctx->b_out,
-                    (void *)ctx->b_amax, (void *)ctx->b_rnorm, ctx->b_flags, ctx->h_buf})
+                    (void *)ctx->b_amax, (void *)ctx->b_rnorm, ctx->b_flags, ctx->h_buf, ctx->b_planes[0],
+                    ctx->b_planes[1]})
         if (b) (void)hipFree(b);
     if (ctx->partials) (void)hipFree(ctx->partials);
     if (ctx->out_dev) (void)hipFree(ctx->out_dev);
@@ -830,6 +852,7 @@ pwa_status pwa_set_amplitudes(pwa_ctx *ctx, pwa_set which, const void *A, int64_
     free_sample(s);
     if (which == PWA_MC) ctx->gram_valid = false;
     ctx->amax_valid = false;
+    ctx->planes_valid[which] = false;
     if (which == PWA_DATA) ctx->rnorm_valid = false;
 
     const size_t row_bytes = 2 * eb * (size_t)ctx->ld;

@@ -109,6 +109,7 @@ struct BatchArgs {
     int32_t tpb;               // tiles (32 rows) per block
     int32_t pstride;           // doubles per (vector, block) partial: 1 + 2k
     int32_t extended;
+    const void *planes[2];     // split operand planes per segment (batch_plane_bytes each)
     const void *wfrag;         // FP16 forward weights in MFMA fragment order
     const float *ascale;       // power-of-two scale per real column (32 * ks entries)
     const double *vscale;      // power-of-two scale of each vector's weights
@@ -149,6 +150,11 @@ hipError_t launch_batch(const BatchArgs &args, bool refine, hipStream_t stream);
 hipError_t launch_batch_refine(const BatchArgs &args, hipStream_t stream);
 size_t batch_flag_words(int64_t n0, int nv, int k);
 hipError_t launch_rownorm(const float *A, int64_t n, int64_t ld, int k, float *out, hipStream_t stream);
+// The batched pass's operand planes of one sample (FP16 hi / lo scaled by ascale,
+// BF16 hi / lo transposed; 32-event tiles) and their size in bytes.
+size_t batch_plane_bytes(int64_t n, int k);
+hipError_t launch_batch_planes(const float *A, int64_t n, int64_t ld, int k, const float *ascale, void *out,
+                               hipStream_t stream);
 constexpr float kRefineC2 = 1.0f / 64.0f;     // largest c^2 (c = 1/8); batch_setup lowers it as sqrt(k) / N_D
 hipError_t launch_batch_combine(const BatchArgs &args, hipStream_t stream);
 // Device-side forward weights from args.V: the per-vector scales, then the
