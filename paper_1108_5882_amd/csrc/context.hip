@@ -996,7 +996,7 @@ pwa_status pwa_hessian(pwa_ctx *ctx, const double *V, double *H) {
     pwa_status st;
     if (need_mc && (st = ensure_gram(ctx)) != PWA_OK) return st;
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ctx->cu_count * 2, (nd + 63) / 64));
-    const size_t n_part = hessian_partial_doubles(k, blocks), n_t = 2 * (size_t)k * k, n_v = 2 * (size_t)k,
+    const size_t n_part = hessian_partial_doubles(k, blocks), n_t = hessian_g_doubles(k), n_v = 2 * (size_t)k,
                  n_h = 4 * (size_t)k * k + 1;
     const size_t doubles = n_part + n_t + n_v + n_h + 1;
     if ((st = grow(ctx, &ctx->h_buf, &ctx->h_cap, sizeof(double) * doubles, "hipMalloc(hessian)"))) return st;

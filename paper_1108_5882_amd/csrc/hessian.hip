@@ -13,8 +13,7 @@
 //   Eq. 2 form:  H = -d2(sum ln I) + N_D (d2S / S - dS dS^T / S^2)
 //   Eq. 3 form:  H = -d2(sum ln I) + d2S
 //
-// One pass over the data rows: each block stages a tile of rows in LDS as
-// FP64, forms z and 1/z^2 per row in FP64 and accumulates its share of T;
+// One pass over the data rows on the FP64 matrix cores (hess_mfma_kernel);
 // the block partials are added in block order, then one block assembles H.
 #include "internal.hpp"
 
@@ -22,201 +21,183 @@ namespace pwa {
 namespace {
 
 constexpr int kHThreads = 256;
-constexpr int kHRows = 32;
-constexpr int kHMaxTiles = 3;     // 2 x 2 entry tiles per thread (k = 64: 528 tiles over 256 threads)
-
 __global__ void hess_clear_kernel(unsigned *flag) { *flag = 0u; }
 
-// Upper-triangle 2 x 2 tile t -> (ta, tc), ta <= tc, of nt tile rows (row-major order).
-__device__ __forceinline__ void tile_index(int t, int nt, int &ta, int &tc) {
-    int a = 0, row = nt;
-    while (t >= row) {
-        t -= row;
-        ++a;
-        --row;
-    }
-    ta = a;
-    tc = a + t;
-}
-
-// T is complex symmetric: each thread accumulates 2 x 2 tiles (ta, tc) of the
-// upper triangle (rows 2 ta, 2 ta + 1, columns 2 tc, 2 tc + 1).  With fewer
-// tiles than threads the block forms RG = 256 / ntile row groups that take every
-// RG-th row of the LDS tile; the groups' sums are added in group order at the
-// end.  z comes from 8 lanes per row.
-template <typename T>
-__global__ __launch_bounds__(kHThreads) void hess_partial_kernel(const T *__restrict__ A, int64_t n, int64_t ld,
-                                                                 int k, const double *__restrict__ V,
-                                                                 double *__restrict__ partials,
-                                                                 unsigned *__restrict__ flag) {
-    __shared__ __attribute__((aligned(16))) double tile[kHRows][2 * PWA_MAX_K + 4];
-    __shared__ __attribute__((aligned(16))) double cw[kHRows][2];   // 1 / z^2 per row (0 for absent rows)
-    __shared__ double red[kHThreads][8];              // row-group sums (one tile per slot then)
-    const int tid = threadIdx.x;
-    const int nt = (k + 1) / 2;                       // tile rows
-    const int ntile = nt * (nt + 1) / 2;
-    const int S = ntile < kHThreads ? ntile : kHThreads;   // tile slots per row group
-    const int RG = kHThreads / S;                     // row groups (threads past RG S idle)
-    const int rg = tid / S, slot = tid % S;
-    const int kk = k * k;
+// Matrix-core pass.  With u_i = 1 / z_i and B_i = A_i u_i (complex, K values),
+// T = sum_i B_i B_i^T (no conjugate).  In real terms, with the row
+// X_i = (Re B_i padded to KP, Im B_i padded to KP) of 2 KP reals,
+//     G = sum_i X_i X_i^T = [[Grr, Gri], [Gri^T, Gii]],
+//     Re T = Grr - Gii,   Im T = Gri + Gri^T,
+// so the pass is a symmetric rank-N update of a 2KP x 2KP FP64 matrix, run as
+// v_mfma_f64_16x16x4f64 on 16 x 16 tiles of its upper triangle.  Per step a
+// block forms X for 64 events in LDS (4 threads per event: z from a quarter
+// of the waves each and a DPP sum, then u and B); the waves then multiply:
+// with few tiles each wave takes every tile for 16 of the 64 events, with
+// many each wave takes every fourth tile for all 64.  The waves' sums are
+// added in wave order and the block writes its full G (lower tiles mirrored).
+template <typename T, int KP>
+__global__ __launch_bounds__(kHThreads) void hess_mfma_kernel(const T *__restrict__ A, int64_t n, int64_t ld, int k,
+                                                              const double *__restrict__ V,
+                                                              double *__restrict__ partials,
+                                                              unsigned *__restrict__ flag) {
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    constexpr int NC = 2 * KP;                  // columns of X
+    constexpr int NT = NC / 16;                 // tile rows
+    constexpr int NTU = NT * (NT + 1) / 2;      // upper-triangle tiles
+    constexpr bool SPLIT_EVENTS = NTU <= 10;
+    constexpr int MAXT = SPLIT_EVENTS ? NTU : (NTU + 3) / 4;
+    constexpr int EV = 64;                      // events per step
+    constexpr int XS = NC + 2;                  // LDS row stride (doubles)
+    constexpr int WPT = KP / 4;                 // waves per thread when forming z and B
+    __shared__ __attribute__((aligned(16))) double X[EV][XS];
+    __shared__ double Gs[SPLIT_EVENTS ? NC : 1][SPLIT_EVENTS ? NC + 1 : 1];   // the waves' sums (split events)
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
     const int64_t r0 = (int64_t)blockIdx.x * chunk;
     const int64_t r1 = r0 + chunk < n ? r0 + chunk : n;
 
-    int tA[kHMaxTiles], tC[kHMaxTiles];
+    // this wave's tiles (p <= q) in upper-triangle order
+    int tp[MAXT], tq[MAXT];
 #pragma unroll
-    for (int m = 0; m < kHMaxTiles; ++m) {
-        const int t = slot + m * S;
-        tA[m] = tC[m] = -1;
-        if (rg < RG && t < ntile) tile_index(t, nt, tA[m], tC[m]);
+    for (int i = 0; i < MAXT; ++i) {
+        const int t = SPLIT_EVENTS ? i : wave + 4 * i;
+        tp[i] = tq[i] = -1;
+        if (t < NTU) {
+            int a = 0, row = NT, r = t;
+            while (r >= row) {
+                r -= row;
+                ++a;
+                --row;
+            }
+            tp[i] = a;
+            tq[i] = a + r;
+        }
     }
-    double acc[kHMaxTiles][8];                         // (re, im) of entries 00, 01, 10, 11
+    d4 acc[MAXT];
 #pragma unroll
-    for (int m = 0; m < kHMaxTiles; ++m)
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc[m][q] = 0.0;
-    bool bad = false;
+    for (int i = 0; i < MAXT; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
 
-    // the next tile's values are loaded into registers while the current one is used
-    constexpr int kPre = kHRows * 2 * PWA_MAX_K / kHThreads;
-    T pre[kPre];
-    const int width = 4 * nt;                          // staged columns (zero beyond 2k)
-    auto fetch = [&](int64_t b) {
-        const int rws = (int)(r1 - b < kHRows ? r1 - b : kHRows);
+    // this thread's V slice
+    const int el = tid >> 2, sub = tid & 3;
+    double vr[WPT], vi[WPT];
 #pragma unroll
-        for (int i = 0; i < kPre; ++i) {
-            const int idx = tid + i * kHThreads;
-            const int r = idx / width, q = idx % width;
-            pre[i] = (idx < kHRows * width && r < rws && q < 2 * k) ? A[2 * (b + r) * ld + q] : T(0);
+    for (int w = 0; w < WPT; ++w) {
+        const int a = sub * WPT + w;
+        vr[w] = a < k ? V[2 * a] : 0.0;
+        vi[w] = a < k ? V[2 * a + 1] : 0.0;
+    }
+    bool bad = false;
+    for (int64_t base = r0; base < r1; base += EV) {
+        const int64_t e = base + el;
+        const bool valid = e < r1;
+        double ar[WPT], ai[WPT];
+        double zr = 0.0, zi = 0.0;
+#pragma unroll
+        for (int w = 0; w < WPT; ++w) {
+            const int a = sub * WPT + w;
+            ar[w] = (valid && a < k) ? (double)A[2 * (e * ld + a)] : 0.0;
+            ai[w] = (valid && a < k) ? (double)A[2 * (e * ld + a) + 1] : 0.0;
+            zr = fma(vr[w], ar[w], fma(-vi[w], ai[w], zr));
+            zi = fma(vr[w], ai[w], fma(vi[w], ar[w], zi));
         }
-    };
-    if (r0 < r1) fetch(r0);
-    for (int64_t base = r0; base < r1; base += kHRows) {
-        const int rows = (int)(r1 - base < kHRows ? r1 - base : kHRows);
-        __syncthreads();
-        // rows as FP64, zero beyond k (an odd k's last tile reads one zero column)
-#pragma unroll
-        for (int i = 0; i < kPre; ++i) {
-            const int idx = tid + i * kHThreads;
-            if (idx < kHRows * width) tile[idx / width][idx % width] = (double)pre[i];
-        }
-        __syncthreads();
-        if (base + kHRows < r1) fetch(base + kHRows);
-        {
-            // z of row tid / 8 from 8 lanes (waves sub, sub + 8, ...), summed over the lanes
-            const int row = tid >> 3, sub = tid & 7;
-            double zr = 0.0, zi = 0.0;
-            if (row < rows)
-                for (int a = sub; a < k; a += 8) {
-                    const double ar = tile[row][2 * a], ai = tile[row][2 * a + 1];
-                    zr = fma(V[2 * a], ar, fma(-V[2 * a + 1], ai, zr));
-                    zi = fma(V[2 * a], ai, fma(V[2 * a + 1], ar, zi));
-                }
-#pragma unroll
-            for (int off = 1; off < 8; off <<= 1) {
-                zr += __shfl_xor(zr, off);
-                zi += __shfl_xor(zi, off);
-            }
-            if (sub == 0) {
-                double wr = 0.0, wi = 0.0;
-                if (row < rows) {
-                    const double I = zr * zr + zi * zi;
-                    if (I > 0.0 && isfinite(I)) {
-                        // 1 / z^2 = conj(z)^2 / I^2
-                        const double i2 = 1.0 / (I * I);
-                        wr = (zr * zr - zi * zi) * i2;
-                        wi = -2.0 * zr * zi * i2;
-                    } else {
-                        bad = true;
-                    }
-                }
-                cw[row][0] = wr;
-                cw[row][1] = wi;
+        zr += __shfl_xor(zr, 1);
+        zi += __shfl_xor(zi, 1);
+        zr += __shfl_xor(zr, 2);
+        zi += __shfl_xor(zi, 2);
+        const double I = zr * zr + zi * zi;
+        double ur = 0.0, ui = 0.0;
+        if (valid) {
+            if (I > 0.0 && isfinite(I)) {
+                ur = zr / I;                         // 1 / z = conj(z) / I
+                ui = -zi / I;
+            } else {
+                bad = true;
             }
         }
+        __syncthreads();                             // the previous step's X is consumed
+#pragma unroll
+        for (int w = 0; w < WPT; ++w) {
+            const int a = sub * WPT + w;
+            X[el][a] = fma(ar[w], ur, -ai[w] * ui);          // Re (A u)
+            X[el][KP + a] = fma(ar[w], ui, ai[w] * ur);      // Im (A u)
+        }
         __syncthreads();
+        // rows of the k-step: 4 events, lane l takes event l / 16 and column l % 16
+        const int er = lane >> 4, ec = lane & 15;
+        if (SPLIT_EVENTS) {
 #pragma unroll
-        for (int m = 0; m < kHMaxTiles; ++m) {
-            if (tA[m] < 0) continue;
-            const int a0 = 2 * tA[m], c0 = 2 * tC[m];
-            double s[8];
+            for (int ks = 0; ks < 4; ++ks) {
+                const double *row = X[16 * wave + 4 * ks + er];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) s[q] = acc[m][q];
-            for (int r = rg; r < rows; r += RG) {
-                const double wr = cw[r][0], wi = cw[r][1];
-                const double x0r = tile[r][2 * a0], x0i = tile[r][2 * a0 + 1];
-                const double x1r = tile[r][2 * a0 + 2], x1i = tile[r][2 * a0 + 3];
-                const double y0r = tile[r][2 * c0], y0i = tile[r][2 * c0 + 1];
-                const double y1r = tile[r][2 * c0 + 2], y1i = tile[r][2 * c0 + 3];
-                // (w x) then times y, for the four entries
-                const double u0r = fma(wr, x0r, -(wi * x0i)), u0i = fma(wr, x0i, wi * x0r);
-                const double u1r = fma(wr, x1r, -(wi * x1i)), u1i = fma(wr, x1i, wi * x1r);
-                s[0] = fma(u0r, y0r, fma(-u0i, y0i, s[0]));
-                s[1] = fma(u0r, y0i, fma(u0i, y0r, s[1]));
-                s[2] = fma(u0r, y1r, fma(-u0i, y1i, s[2]));
-                s[3] = fma(u0r, y1i, fma(u0i, y1r, s[3]));
-                s[4] = fma(u1r, y0r, fma(-u1i, y0i, s[4]));
-                s[5] = fma(u1r, y0i, fma(u1i, y0r, s[5]));
-                s[6] = fma(u1r, y1r, fma(-u1i, y1i, s[6]));
-                s[7] = fma(u1r, y1i, fma(u1i, y1r, s[7]));
+                for (int i = 0; i < MAXT; ++i)
+                    acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(row[16 * tp[i] + ec], row[16 * tq[i] + ec], acc[i],
+                                                                  0, 0, 0);
             }
+        } else {
+#pragma unroll 4
+            for (int ks = 0; ks < EV / 4; ++ks) {
+                const double *row = X[4 * ks + er];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) acc[m][q] = s[q];
+                for (int i = 0; i < MAXT; ++i)
+                    if (tp[i] >= 0)
+                        acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(row[16 * tp[i] + ec], row[16 * tq[i] + ec],
+                                                                      acc[i], 0, 0, 0);
+            }
         }
     }
     if (bad) atomicOr(flag, 1u);
-    // add the row groups in group order; with RG > 1 there are fewer tiles than
-    // slots, so each slot holds only its first tile
-    __syncthreads();
-    if (RG > 1) {
+    // FP64 MFMA result layout: item j of lane l is row l / 16 + 4 j, column l % 16 of a tile
+    const int rb = lane >> 4, cb = lane & 15;
+    double *out = partials + (int64_t)blockIdx.x * NC * NC;
+    if (SPLIT_EVENTS) {
+        // every wave holds every tile for its quarter of the events: their sums in wave order
+        for (int idx = tid; idx < NC * NC; idx += kHThreads) Gs[idx / NC][idx % NC] = 0.0;
+        for (int w = 0; w < 4; ++w) {
+            __syncthreads();
+            if (wave == w) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) red[tid][q] = acc[0][q];
+                for (int i = 0; i < MAXT; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) Gs[16 * tp[i] + rb + 4 * j][16 * tq[i] + cb] += acc[i][j];
+            }
+        }
         __syncthreads();
-        if (rg == 0) {
+        // block partial: the full G (lower tiles as the transposes of the upper ones)
+        for (int idx = tid; idx < NC * NC; idx += kHThreads) {
+            const int r = idx / NC, c = idx % NC;
+            out[idx] = (r >> 4) <= (c >> 4) ? Gs[r][c] : Gs[c][r];
+        }
+    } else {
+        // each tile belongs to one wave: written with its transpose
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                double v = red[slot][q];
-                for (int g = 1; g < RG; ++g) v += red[g * S + slot][q];
-                acc[0][q] = v;
+        for (int i = 0; i < MAXT; ++i) {
+            if (tp[i] < 0) continue;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = 16 * tp[i] + rb + 4 * j, c = 16 * tq[i] + cb;
+                out[(int64_t)r * NC + c] = acc[i][j];
+                if (tp[i] != tq[i]) out[(int64_t)c * NC + r] = acc[i][j];
             }
         }
     }
-    if (rg != 0) return;
-    double *out = partials + (int64_t)blockIdx.x * 2 * kk;
-#pragma unroll
-    for (int m = 0; m < kHMaxTiles; ++m) {
-        if (tA[m] < 0) continue;
-#pragma unroll
-        for (int ea = 0; ea < 2; ++ea)
-#pragma unroll
-            for (int ec = 0; ec < 2; ++ec) {
-                const int a = 2 * tA[m] + ea, c = 2 * tC[m] + ec;
-                if (a >= k || c >= k) continue;
-                const double vr = acc[m][4 * ea + 2 * ec], vi = acc[m][4 * ea + 2 * ec + 1];
-                out[2 * (a * k + c)] = vr;
-                out[2 * (a * k + c) + 1] = vi;
-                out[2 * (c * k + a)] = vr;          // T is symmetric
-                out[2 * (c * k + a) + 1] = vi;
-            }
-    }
 }
 
-// T = sum of the block partials: one block per entry, fixed-order tree.
+// G = sum of the block partials: one block per entry, fixed-order tree.
 constexpr int kFinThreads = 64;
 __global__ __launch_bounds__(kFinThreads) void hess_finish_kernel(const double *__restrict__ partials, int nblocks,
-                                                                  int k, double *__restrict__ Tm) {
-    const int kk2 = 2 * k * k;
+                                                                  int entries, double *__restrict__ Tm) {
     const int e = blockIdx.x;
     double s = 0.0;
 #pragma unroll 4
-    for (int b = threadIdx.x; b < nblocks; b += kFinThreads) s += partials[(int64_t)b * kk2 + e];
+    for (int b = threadIdx.x; b < nblocks; b += kFinThreads) s += partials[(int64_t)b * entries + e];
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
     if (threadIdx.x == 0) Tm[e] = s;
 }
 
-// One block: H (2k x 2k, row-major) from T, M and V; H[2k * 2k] = status flags.
-__global__ void hess_assemble_kernel(const double *__restrict__ Tm, const double *__restrict__ M,
+// One block: H (2k x 2k, row-major) from G (2 kp x 2 kp, see hess_mfma_kernel),
+// M and V; H[2k * 2k] = status flags.
+__global__ void hess_assemble_kernel(const double *__restrict__ Gm, int kp, const double *__restrict__ M,
                                      const double *__restrict__ V, int k, double nd, int extended,
                                      const unsigned *__restrict__ flag, double *__restrict__ H) {
     __shared__ double mv[2 * PWA_MAX_K];      // M V
@@ -243,7 +224,10 @@ __global__ void hess_assemble_kernel(const double *__restrict__ Tm, const double
     for (int idx = tid; idx < n2 * n2; idx += blockDim.x) {
         const int m = idx / n2, n = idx % n2;
         const int a = m >> 1, c = n >> 1, pa = m & 1, pc = n & 1;
-        const double tr = Tm[2 * (a * k + c)], ti = Tm[2 * (a * k + c) + 1];
+        // Re T = Grr - Gii, Im T = Gri + Gri^T
+        const int nc = 2 * kp;
+        const double tr = Gm[a * nc + c] - Gm[(kp + a) * nc + kp + c];
+        const double ti = Gm[a * nc + kp + c] + Gm[(kp + a) * nc + c];
         const double mr = M[2 * (a * k + c)], mi = M[2 * (a * k + c) + 1];
         // block entries of d2(sum ln I) and d2S for (x or y of a, x or y of c)
         double hl, d2s;
@@ -270,30 +254,47 @@ __global__ void hess_assemble_kernel(const double *__restrict__ Tm, const double
 
 }  // namespace
 
-size_t hessian_partial_doubles(int k, int blocks) { return (size_t)blocks * 2 * k * k; }
+int hessian_kp(int k) { return 8 * ((k + 7) / 8); }
+size_t hessian_g_doubles(int k) { return (size_t)(2 * hessian_kp(k)) * (size_t)(2 * hessian_kp(k)); }
+size_t hessian_partial_doubles(int k, int blocks) { return (size_t)blocks * hessian_g_doubles(k); }
+
+template <typename T>
+hipError_t launch_hess_mfma(const T *A, int64_t n, int64_t ld, int k, const double *V, double *partials,
+                            unsigned *flag, int blocks, hipStream_t s) {
+    switch (hessian_kp(k)) {
+#define PWA_HESS_CASE(KP_)                                                                                   \
+    case KP_:                                                                                                \
+        hipLaunchKernelGGL((hess_mfma_kernel<T, KP_>), dim3(blocks), dim3(kHThreads), 0, s, A, n, ld, k, V, \
+                           partials, flag);                                                                  \
+        break;
+        PWA_HESS_CASE(8) PWA_HESS_CASE(16) PWA_HESS_CASE(24) PWA_HESS_CASE(32)
+        PWA_HESS_CASE(40) PWA_HESS_CASE(48) PWA_HESS_CASE(56) PWA_HESS_CASE(64)
+#undef PWA_HESS_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_hessian(pwa_prec prec, const void *A, int64_t n, int64_t ld, int k, const double *V_dev,
-                          const double *M, double nd, int extended, double *partials, int blocks, double *Tm,
+                          const double *M, double nd, int extended, double *partials, int blocks, double *Gm,
                           unsigned *flag, double *H, hipStream_t stream) {
     if (k < 1 || k > PWA_MAX_K || blocks < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(hess_clear_kernel, dim3(1), dim3(1), 0, stream, flag);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (n > 0) {
-        if (prec == PWA_F32)
-            hipLaunchKernelGGL(hess_partial_kernel<float>, dim3(blocks), dim3(kHThreads), 0, stream,
-                               static_cast<const float *>(A), n, ld, k, V_dev, partials, flag);
-        else
-            hipLaunchKernelGGL(hess_partial_kernel<double>, dim3(blocks), dim3(kHThreads), 0, stream,
-                               static_cast<const double *>(A), n, ld, k, V_dev, partials, flag);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        e = prec == PWA_F32
+                ? launch_hess_mfma(static_cast<const float *>(A), n, ld, k, V_dev, partials, flag, blocks, stream)
+                : launch_hess_mfma(static_cast<const double *>(A), n, ld, k, V_dev, partials, flag, blocks, stream);
+        if (e != hipSuccess) return e;
     } else {
         blocks = 0;
     }
-    const int kk2 = 2 * k * k;
-    hipLaunchKernelGGL(hess_finish_kernel, dim3(kk2), dim3(kFinThreads), 0, stream, partials, blocks, k, Tm);
+    const int entries = (int)hessian_g_doubles(k);
+    hipLaunchKernelGGL(hess_finish_kernel, dim3(entries), dim3(kFinThreads), 0, stream, partials, blocks, entries, Gm);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(hess_assemble_kernel, dim3(1), dim3(256), 0, stream, Tm, M, V_dev, k, nd, extended, flag, H);
+    hipLaunchKernelGGL(hess_assemble_kernel, dim3(1), dim3(256), 0, stream, Gm, hessian_kp(k), M, V_dev, k, nd,
+                       extended, flag, H);
     return hipGetLastError();
 }
 

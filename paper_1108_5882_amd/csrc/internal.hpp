@@ -246,11 +246,13 @@ size_t gram_partial_doubles(int k, int blocks);
 // MC matrix M (k x k complex, FP64, 1/N_gen folded in), nd data events and the
 // likelihood form; writes H (2k x 2k row-major, then one status double: 0 ok,
 // 1 domain failure).  partials: hessian_partial_doubles(k, blocks) doubles;
-// Tm: 2 k^2 doubles; flag: one unsigned.
+// Gm: hessian_g_doubles(k) doubles (the summed real 2 kp x 2 kp matrix G of
+// the pass, kp = k rounded up to a multiple of 8); flag: one unsigned.
 hipError_t launch_hessian(pwa_prec prec, const void *A, int64_t n, int64_t ld, int k, const double *V_dev,
-                          const double *M, double nd, int extended, double *partials, int blocks, double *Tm,
+                          const double *M, double nd, int extended, double *partials, int blocks, double *Gm,
                           unsigned *flag, double *H, hipStream_t stream);
 size_t hessian_partial_doubles(int k, int blocks);
+size_t hessian_g_doubles(int k);
 
 // ---------------------------------------------------------------- surrogate MLP
 // Device buffers of the in -> hidden -> hidden -> 1 network (FP32 master
