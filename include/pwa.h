@@ -314,6 +314,10 @@ pwa_status pwa_kernel_time(pwa_ctx *ctx, double *avg_ms, int64_t *count);
  * per-vector combine kernel. */
 pwa_status pwa_batch_kernel_time(pwa_ctx *ctx, double *avg_ms, int64_t *count);
 
+/* Same for pwa_hessian: all of its kernels (the data pass and the sums and
+ * assembly after it), without the V upload and the H readback. */
+pwa_status pwa_hessian_kernel_time(pwa_ctx *ctx, double *avg_ms, int64_t *count);
+
 /* ------------------------------------------------------------------------
  * Amplitudes formed on the device from each event's kinematics, so that the
  * masses and widths of the resonances can be fit parameters (Section 2: the

@@ -28,7 +28,7 @@ EXPORTS = [
     "pwa_nll_grad", "pwa_nll_grad_async", "pwa_nll_batch", "pwa_nll_batch_async", "pwa_hessian", "pwa_last_flags",
     "pwa_last_error",
     "pwa_layout_ld", "pwa_set_timing", "pwa_kernel_time", "pwa_get_stream_cfg",
-    "pwa_set_stream_cfg", "pwa_autotune", "pwa_batch_kernel_time",
+    "pwa_set_stream_cfg", "pwa_autotune", "pwa_batch_kernel_time", "pwa_hessian_kernel_time",
     "pwa_multi_create", "pwa_multi_destroy", "pwa_multi_eval", "pwa_multi_reset", "pwa_multi_step",
     "pwa_multi_get", "pwa_multi_autotune", "pwa_multi_last_error", "pwa_batch_fit",
     "pwa_mlp_param_count", "pwa_mlp_create", "pwa_mlp_destroy", "pwa_mlp_set_params", "pwa_mlp_get_params",
@@ -115,6 +115,7 @@ def load(path: str = LIB_PATH):
         "pwa_set_timing": [P, ctypes.c_int],
         "pwa_kernel_time": [P, ctypes.POINTER(D), ctypes.POINTER(I64)],
         "pwa_batch_kernel_time": [P, ctypes.POINTER(D), ctypes.POINTER(I64)],
+        "pwa_hessian_kernel_time": [P, ctypes.POINTER(D), ctypes.POINTER(I64)],
         "pwa_get_stream_cfg": [P, ctypes.POINTER(StreamCfg)],
         "pwa_set_stream_cfg": [P, ctypes.POINTER(StreamCfg)],
         "pwa_autotune": [P, I32, ctypes.POINTER(StreamCfg), ctypes.POINTER(D)],
@@ -506,6 +507,13 @@ class Context:
         ms = ctypes.c_double()
         n = ctypes.c_int64()
         self._check(self.lib.pwa_batch_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def hessian_kernel_time(self):
+        """(average ms, count) of the Hessian's kernels (per call) since the last query."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._check(self.lib.pwa_hessian_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
 
 

@@ -78,6 +78,7 @@ struct pwa_ctx {
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> batch_events;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> hess_events;
     std::vector<hipEvent_t> event_pool;   // timing events kept for reuse
 
     // batched (many-V) path: per-wave FP16 scales of the amplitudes, device scratch
@@ -778,7 +779,7 @@ pwa_status pwa_destroy(pwa_ctx *ctx) {
     DeviceGuard dg(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     for (auto &s : ctx->s) free_sample(s);
-    for (auto *list : {&ctx->events, &ctx->batch_events})
+    for (auto *list : {&ctx->events, &ctx->batch_events, &ctx->hess_events})
         for (auto &ev : *list) {
             (void)hipEventDestroy(ev.first);
             (void)hipEventDestroy(ev.second);
@@ -995,21 +996,31 @@ pwa_status pwa_hessian(pwa_ctx *ctx, const double *V, double *H) {
     if (need_mc && ctx->s[1].n == 0 && nd > 0) return fail(ctx, PWA_E_STATE, "MC sample is empty: no normalisation");
     pwa_status st;
     if (need_mc && (st = ensure_gram(ctx)) != PWA_OK) return st;
-    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ctx->cu_count * 2, (nd + 63) / 64));
-    const size_t n_part = hessian_partial_doubles(k, blocks), n_t = hessian_g_doubles(k), n_v = 2 * (size_t)k,
-                 n_h = 4 * (size_t)k * k + 1;
-    const size_t doubles = n_part + n_t + n_v + n_h + 1;
+    const int blocks = hessian_blocks(ctx->prec, k, ctx->cu_count, nd);
+    const size_t n_work = hessian_work_doubles(k, blocks), n_v = 2 * (size_t)k, n_h = 4 * (size_t)k * k + 1;
+    const size_t doubles = n_work + n_v + n_h + 1;
     if ((st = grow(ctx, &ctx->h_buf, &ctx->h_cap, sizeof(double) * doubles, "hipMalloc(hessian)"))) return st;
-    double *part = static_cast<double *>(ctx->h_buf);
-    double *Tm = part + n_part, *Vd = Tm + n_t, *Hd = Vd + n_v;
+    double *work = static_cast<double *>(ctx->h_buf);
+    double *Vd = work + n_work, *Hd = Vd + n_v;
     unsigned *flag = reinterpret_cast<unsigned *>(Hd + n_h);
     PWA_HIP(ctx, hipMemcpyAsync(Vd, V, sizeof(double) * n_v, hipMemcpyHostToDevice, ctx->stream),
             "hipMemcpyAsync(V)");
-    // without MC rows (Eq. 2 form, no data) the normalisation term is absent: T (zero) stands in for M
-    const double *M = need_mc ? ctx->gram : Tm;
-    hipError_t e = launch_hessian(ctx->prec, ctx->s[0].A, nd, ctx->ld, k, Vd, M, (double)nd, ctx->extended, part,
-                                  blocks, Tm, flag, Hd, ctx->stream);
+    // without MC rows (Eq. 2 form, no data) there is no normalisation term
+    const double *M = need_mc ? ctx->gram : nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ctx->timing) {
+        if ((st = take_event(ctx, &e0)) != PWA_OK) return st;
+        if ((st = take_event(ctx, &e1)) != PWA_OK) {
+            ctx->event_pool.push_back(e0);
+            return st;
+        }
+        ctx->hess_events.emplace_back(e0, e1);
+        PWA_HIP(ctx, hipEventRecord(e0, ctx->stream), "hipEventRecord");
+    }
+    hipError_t e = launch_hessian(ctx->prec, ctx->s[0].A, nd, ctx->ld, k, Vd, M, (double)nd, ctx->extended, work,
+                                  blocks, flag, Hd, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "hessian launch");
+    if (ctx->timing) PWA_HIP(ctx, hipEventRecord(e1, ctx->stream), "hipEventRecord");
     std::vector<double> h(n_h);
     PWA_HIP(ctx, hipMemcpyAsync(h.data(), Hd, sizeof(double) * n_h, hipMemcpyDeviceToHost, ctx->stream),
             "hipMemcpyAsync(H)");
@@ -1173,6 +1184,11 @@ pwa_status pwa_kernel_time(pwa_ctx *ctx, double *avg_ms, int64_t *count) {
 pwa_status pwa_batch_kernel_time(pwa_ctx *ctx, double *avg_ms, int64_t *count) {
     if (!ctx) return fail(nullptr, PWA_E_INVAL, "null context");
     return drain_events(ctx, ctx->batch_events, avg_ms, count);
+}
+
+pwa_status pwa_hessian_kernel_time(pwa_ctx *ctx, double *avg_ms, int64_t *count) {
+    if (!ctx) return fail(nullptr, PWA_E_INVAL, "null context");
+    return drain_events(ctx, ctx->hess_events, avg_ms, count);
 }
 
 }  // extern "C"

@@ -13,288 +13,501 @@
 //   Eq. 2 form:  H = -d2(sum ln I) + N_D (d2S / S - dS dS^T / S^2)
 //   Eq. 3 form:  H = -d2(sum ln I) + d2S
 //
-// One pass over the data rows on the FP64 matrix cores (hess_mfma_kernel);
-// the block partials are added in block order, then one block assembles H.
+// Launches: a prologue (status word, M V), the data pass on the FP64 matrix
+// cores (hess_mfma_kernel, one launch per group of at most 21 output tiles),
+// a two-level fixed-order sum of the block partials, and the assembly of H.
+#include <utility>
+
 #include "internal.hpp"
 
 namespace pwa {
 namespace {
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
 constexpr int kHThreads = 256;
-__global__ void hess_clear_kernel(unsigned *flag) { *flag = 0u; }
+constexpr int kHWaves = kHThreads / 64;
+constexpr int kHRows = 16;        // events per wave per step (four k-steps of the 16x16x4 MFMA)
+constexpr int kHMaxTiles = 21;    // accumulator tiles per wave in one launch
+constexpr int kHChunk = 32;       // block partials per first-level sum
 
-// Matrix-core pass.  With u_i = 1 / z_i and B_i = A_i u_i (complex, K values),
-// T = sum_i B_i B_i^T (no conjugate).  In real terms, with the row
-// X_i = (Re B_i padded to KP, Im B_i padded to KP) of 2 KP reals,
-//     G = sum_i X_i X_i^T = [[Grr, Gri], [Gri^T, Gii]],
-//     Re T = Grr - Gii,   Im T = Gri + Gri^T,
-// so the pass is a symmetric rank-N update of a 2KP x 2KP FP64 matrix, run as
-// v_mfma_f64_16x16x4f64 on 16 x 16 tiles of its upper triangle.  Per step a
-// block forms X for 64 events in LDS (4 threads per event: z from a quarter
-// of the waves each and a DPP sum, then u and B); the waves then multiply:
-// with few tiles each wave takes every tile for 16 of the 64 events, with
-// many each wave takes every fourth tile for all 64.  The waves' sums are
-// added in wave order and the block writes its full G (lower tiles mirrored).
-template <typename T, int KP>
-__global__ __launch_bounds__(kHThreads) void hess_mfma_kernel(const T *__restrict__ A, int64_t n, int64_t ld, int k,
-                                                              const double *__restrict__ V,
-                                                              double *__restrict__ partials,
-                                                              unsigned *__restrict__ flag) {
-    typedef double d4 __attribute__((ext_vector_type(4)));
-    constexpr int NC = 2 * KP;                  // columns of X
-    constexpr int NT = NC / 16;                 // tile rows
-    constexpr int NTU = NT * (NT + 1) / 2;      // upper-triangle tiles
-    constexpr bool SPLIT_EVENTS = NTU <= 10;
-    constexpr int MAXT = SPLIT_EVENTS ? NTU : (NTU + 3) / 4;
-    constexpr int EV = 64;                      // events per step
-    constexpr int XS = NC + 2;                  // LDS row stride (doubles)
-    constexpr int WPT = KP / 4;                 // waves per thread when forming z and B
-    __shared__ __attribute__((aligned(16))) double X[EV][XS];
-    __shared__ double Gs[SPLIT_EVENTS ? NC : 1][SPLIT_EVENTS ? NC + 1 : 1];   // the waves' sums (split events)
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-    const int64_t r0 = (int64_t)blockIdx.x * chunk;
-    const int64_t r1 = r0 + chunk < n ? r0 + chunk : n;
+// Output tiles: the upper triangle of the NT x NT grid of 16 x 16 tiles of G,
+// numbered row by row.
+constexpr int tile_p(int t, int nt) {
+    int p = 0;
+    while (t >= nt - p) {
+        t -= nt - p;
+        ++p;
+    }
+    return p;
+}
+constexpr int tile_q(int t, int nt) {
+    int p = 0;
+    while (t >= nt - p) {
+        t -= nt - p;
+        ++p;
+    }
+    return p + t;
+}
+constexpr int tile_count(int nt) { return nt * (nt + 1) / 2; }
+constexpr int tile_groups(int nt) { return (tile_count(nt) + kHMaxTiles - 1) / kHMaxTiles; }
+// Wave slab layout: logical column c of event row r sits at r * XS + sh(r) + c
+// with sh(r) = 8 ((r >> 1) & 1) + 4 ((r >> 2) & 1) and XS = 16 mod 32
+// doubles.  The row writes (lanes: 8 rows x 4 consecutive columns per
+// half-wave) and the MFMA operand reads (lanes: 2 rows x 16 consecutive
+// columns per half-wave) then touch distinct banks, and both take one base
+// address per lane plus immediate offsets.
+constexpr int slab_stride(int nc) {
+    int x = nc + 12;
+    while (x % 32 != 16) ++x;
+    return x;
+}
+__device__ __forceinline__ int slab_shift(int r) { return 8 * ((r >> 1) & 1) + 4 * ((r >> 2) & 1); }
 
-    // this wave's tiles (p <= q) in upper-triangle order
-    int tp[MAXT], tq[MAXT];
-#pragma unroll
-    for (int i = 0; i < MAXT; ++i) {
-        const int t = SPLIT_EVENTS ? i : wave + 4 * i;
-        tp[i] = tq[i] = -1;
-        if (t < NTU) {
-            int a = 0, row = NT, r = t;
-            while (r >= row) {
-                r -= row;
-                ++a;
-                --row;
-            }
-            tp[i] = a;
-            tq[i] = a + r;
-        }
-    }
-    d4 acc[MAXT];
-#pragma unroll
-    for (int i = 0; i < MAXT; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
-
-    // this thread's V slice
-    const int el = tid >> 2, sub = tid & 3;
-    double vr[WPT], vi[WPT];
-#pragma unroll
-    for (int w = 0; w < WPT; ++w) {
-        const int a = sub * WPT + w;
-        vr[w] = a < k ? V[2 * a] : 0.0;
-        vi[w] = a < k ? V[2 * a + 1] : 0.0;
-    }
-    bool bad = false;
-    for (int64_t base = r0; base < r1; base += EV) {
-        const int64_t e = base + el;
-        const bool valid = e < r1;
-        double ar[WPT], ai[WPT];
-        double zr = 0.0, zi = 0.0;
-#pragma unroll
-        for (int w = 0; w < WPT; ++w) {
-            const int a = sub * WPT + w;
-            ar[w] = (valid && a < k) ? (double)A[2 * (e * ld + a)] : 0.0;
-            ai[w] = (valid && a < k) ? (double)A[2 * (e * ld + a) + 1] : 0.0;
-            zr = fma(vr[w], ar[w], fma(-vi[w], ai[w], zr));
-            zi = fma(vr[w], ai[w], fma(vi[w], ar[w], zi));
-        }
-        zr += __shfl_xor(zr, 1);
-        zi += __shfl_xor(zi, 1);
-        zr += __shfl_xor(zr, 2);
-        zi += __shfl_xor(zi, 2);
-        const double I = zr * zr + zi * zi;
-        double ur = 0.0, ui = 0.0;
-        if (valid) {
-            if (I > 0.0 && isfinite(I)) {
-                ur = zr / I;                         // 1 / z = conj(z) / I
-                ui = -zi / I;
-            } else {
-                bad = true;
-            }
-        }
-        __syncthreads();                             // the previous step's X is consumed
-#pragma unroll
-        for (int w = 0; w < WPT; ++w) {
-            const int a = sub * WPT + w;
-            X[el][a] = fma(ar[w], ur, -ai[w] * ui);          // Re (A u)
-            X[el][KP + a] = fma(ar[w], ui, ai[w] * ur);      // Im (A u)
-        }
-        __syncthreads();
-        // rows of the k-step: 4 events, lane l takes event l / 16 and column l % 16
-        const int er = lane >> 4, ec = lane & 15;
-        if (SPLIT_EVENTS) {
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                const double *row = X[16 * wave + 4 * ks + er];
-#pragma unroll
-                for (int i = 0; i < MAXT; ++i)
-                    acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(row[16 * tp[i] + ec], row[16 * tq[i] + ec], acc[i],
-                                                                  0, 0, 0);
-            }
-        } else {
-#pragma unroll 4
-            for (int ks = 0; ks < EV / 4; ++ks) {
-                const double *row = X[4 * ks + er];
-#pragma unroll
-                for (int i = 0; i < MAXT; ++i)
-                    if (tp[i] >= 0)
-                        acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(row[16 * tp[i] + ec], row[16 * tq[i] + ec],
-                                                                      acc[i], 0, 0, 0);
-            }
-        }
-    }
-    if (bad) atomicOr(flag, 1u);
-    // FP64 MFMA result layout: item j of lane l is row l / 16 + 4 j, column l % 16 of a tile
-    const int rb = lane >> 4, cb = lane & 15;
-    double *out = partials + (int64_t)blockIdx.x * NC * NC;
-    if (SPLIT_EVENTS) {
-        // every wave holds every tile for its quarter of the events: their sums in wave order
-        for (int idx = tid; idx < NC * NC; idx += kHThreads) Gs[idx / NC][idx % NC] = 0.0;
-        for (int w = 0; w < 4; ++w) {
-            __syncthreads();
-            if (wave == w) {
-#pragma unroll
-                for (int i = 0; i < MAXT; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) Gs[16 * tp[i] + rb + 4 * j][16 * tq[i] + cb] += acc[i][j];
-            }
-        }
-        __syncthreads();
-        // block partial: the full G (lower tiles as the transposes of the upper ones)
-        for (int idx = tid; idx < NC * NC; idx += kHThreads) {
-            const int r = idx / NC, c = idx % NC;
-            out[idx] = (r >> 4) <= (c >> 4) ? Gs[r][c] : Gs[c][r];
-        }
-    } else {
-        // each tile belongs to one wave: written with its transpose
-#pragma unroll
-        for (int i = 0; i < MAXT; ++i) {
-            if (tp[i] < 0) continue;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int r = 16 * tp[i] + rb + 4 * j, c = 16 * tq[i] + cb;
-                out[(int64_t)r * NC + c] = acc[i][j];
-                if (tp[i] != tq[i]) out[(int64_t)c * NC + r] = acc[i][j];
-            }
-        }
-    }
+// Lane exchange inside groups of four lanes (DPP quad permutation): 0xB1
+// swaps neighbours (lane ^ 1), 0x4E swaps pairs (lane ^ 2).
+template <int CTRL>
+__device__ __forceinline__ double quad_swap(double x) {
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
-// G = sum of the block partials: one block per entry, fixed-order tree.
-constexpr int kFinThreads = 64;
-__global__ __launch_bounds__(kFinThreads) void hess_finish_kernel(const double *__restrict__ partials, int nblocks,
-                                                                  int entries, double *__restrict__ Tm) {
-    const int e = blockIdx.x;
-    double s = 0.0;
-#pragma unroll 4
-    for (int b = threadIdx.x; b < nblocks; b += kFinThreads) s += partials[(int64_t)b * entries + e];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
-    if (threadIdx.x == 0) Tm[e] = s;
+template <typename T> struct Pair;
+template <> struct Pair<float> { typedef float v __attribute__((ext_vector_type(2))); };
+template <> struct Pair<double> { typedef double v __attribute__((ext_vector_type(2))); };
+
+// acc[I] += X^T X on tile T0 + I for the four events of one k-step; colv[c]
+// holds column block c of this lane's event row.
+template <int NT, int T0, int... I>
+__device__ __forceinline__ void mfma_tiles(d4 *acc, const double *colv, std::integer_sequence<int, I...>) {
+    ((acc[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(colv[std::integral_constant<int, tile_p(T0 + I, NT)>::value],
+                                                    colv[std::integral_constant<int, tile_q(T0 + I, NT)>::value],
+                                                    acc[I], 0, 0, 0)),
+     ...);
 }
 
-// One block: H (2k x 2k, row-major) from G (2 kp x 2 kp, see hess_mfma_kernel),
-// M and V; H[2k * 2k] = status flags.
-__global__ void hess_assemble_kernel(const double *__restrict__ Gm, int kp, const double *__restrict__ M,
-                                     const double *__restrict__ V, int k, double nd, int extended,
-                                     const unsigned *__restrict__ flag, double *__restrict__ H) {
-    __shared__ double mv[2 * PWA_MAX_K];      // M V
-    __shared__ double s_S;
-    const int tid = threadIdx.x, n2 = 2 * k;
-    for (int a = tid; a < k; a += blockDim.x) {
-        double re = 0.0, im = 0.0;
-        for (int c = 0; c < k; ++c) {
-            const double mr = M[2 * (a * k + c)], mi = M[2 * (a * k + c) + 1];
-            re = fma(mr, V[2 * c], fma(-mi, V[2 * c + 1], re));
-            im = fma(mr, V[2 * c + 1], fma(mi, V[2 * c], im));
-        }
+// Prologue: status word and (M V)_a, one wave per wave index a (M may be null:
+// no normalisation term).
+__global__ __launch_bounds__(64) void hess_prologue_kernel(const double *__restrict__ M,
+                                                           const double *__restrict__ V, int k,
+                                                           double *__restrict__ mv, unsigned *__restrict__ flag) {
+    const int a = blockIdx.x, c = threadIdx.x;
+    if (a == 0 && c == 0) *flag = 0u;
+    double re = 0.0, im = 0.0;
+    if (M && c < k) {
+        const double mr = M[2 * (a * k + c)], mi = M[2 * (a * k + c) + 1];
+        re = fma(mr, V[2 * c], -mi * V[2 * c + 1]);
+        im = fma(mr, V[2 * c + 1], mi * V[2 * c]);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        re += __shfl_xor(re, off);
+        im += __shfl_xor(im, off);
+    }
+    if (c == 0) {
         mv[2 * a] = re;
         mv[2 * a + 1] = im;
     }
+}
+
+// Data pass on the FP64 matrix cores.  With u_i = 1 / z_i and B_i = A_i u_i
+// (complex, K values), T = sum_i B_i B_i^T (no conjugate).  In real terms,
+// with the row X_i = (Re B_i padded to KP, Im B_i padded to KP) of NC = 2 KP
+// reals,
+//     G = sum_i X_i X_i^T = [[Grr, Gri], [Gri^T, Gii]],
+//     Re T = Grr - Gii,   Im T = Gri + Gri^T,
+// a symmetric rank-N update of an NC x NC FP64 matrix, run as
+// v_mfma_f64_16x16x4f64 on the 16 x 16 tiles T0 .. T0 + NTL - 1 of its upper
+// triangle.  Every wave works alone on 16 events per step: four lanes per
+// event form z (each a quarter of the waves, then two lane swaps), u and the
+// row X in the wave's own LDS slab, then the wave multiplies its slab into
+// all of its tiles while the next step's amplitude rows are in flight (no
+// block barrier inside the loop).  At the end the four waves' tiles are added
+// in wave order and the block writes them to its partial (tile-major, NTU
+// tiles of 256 doubles).  Per event the pass computes 4 K (K + 1) flops of the
+// symmetric contraction plus about 14 K for z, u and B.
+template <typename T, int KP, int T0, int NTL>
+__global__ __launch_bounds__(kHThreads) void hess_mfma_kernel(const T *__restrict__ A, int64_t n, int64_t ld, int k,
+                                                              const double *__restrict__ V, int ntu,
+                                                              double *__restrict__ partials,
+                                                              unsigned *__restrict__ flag) {
+    constexpr int NC = 2 * KP;
+    constexpr int NT = NC / 16;
+    constexpr int XS = slab_stride(NC);
+    constexpr int WPT = KP / 4;                         // waves per lane when forming z and B
+    constexpr int STEP = kHWaves * kHRows;              // events per block step
+    constexpr bool V_LDS = WPT > 4;                     // V from LDS (fewer live registers) at large K
+    constexpr int SLAB = kHRows * XS;                   // doubles of one wave's slab
+    static_assert(NTL * 256 <= kHWaves * SLAB, "the tile sums must fit in the slabs");
+    typedef typename Pair<T>::v TP;
+    __shared__ __attribute__((aligned(16))) double lds[kHWaves * SLAB];
+    __shared__ __attribute__((aligned(16))) double vs[V_LDS ? 2 * KP : 2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double *X = lds + wave * SLAB;                      // this wave's slab
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * chunk;
+    const int64_t r1 = r0 + chunk < n ? r0 + chunk : n;
+    // forming: event row of the slab and the waves a = 4 w + sub
+    const int row = lane >> 2, sub = lane & 3;
+    const int wofs = row * XS + slab_shift(row) + sub;
+    // multiplying: lane (er, ec) feeds event row 4 ks + er, column ec of a tile;
+    // slab_shift(4 ks + er) = 8 (er >> 1) + 4 (ks & 1)
+    const int er = lane >> 4, ec = lane & 15;
+    const int mofs = er * XS + 8 * (er >> 1) + ec;
+
+    double vr[V_LDS ? 1 : WPT], vi[V_LDS ? 1 : WPT];
+    if constexpr (V_LDS) {
+        for (int i = tid; i < 2 * KP; i += kHThreads) vs[i] = i < 2 * k ? V[i] : 0.0;
+        __syncthreads();
+    } else {
+#pragma unroll
+        for (int w = 0; w < WPT; ++w) {
+            const int a = 4 * w + sub;
+            vr[w] = a < k ? V[2 * a] : 0.0;
+            vi[w] = a < k ? V[2 * a + 1] : 0.0;
+        }
+    }
+    d4 acc[NTL];
+#pragma unroll
+    for (int i = 0; i < NTL; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+
+    // amplitudes of event e (zero outside the block's rows or beyond k).  With
+    // rows of at least KP elements every load stays inside its row; otherwise
+    // the element index is clamped.  Either way the loads need no branch.
+    const bool wide = ld >= KP;
+    auto fetch = [&](TP (&dst)[WPT], int64_t e) {
+        const bool ok_e = e < r1;
+        const T *rp = A + 2 * ((e < n ? e : n - 1) * ld);
+        if (wide) {
+            const TP *q = reinterpret_cast<const TP *>(rp) + sub;
+#pragma unroll
+            for (int w = 0; w < WPT; ++w) {
+                const TP v = q[4 * w];
+                dst[w] = (ok_e && 4 * w + sub < k) ? v : TP{};
+            }
+        } else {
+#pragma unroll
+            for (int w = 0; w < WPT; ++w) {
+                const int a = 4 * w + sub;
+                const TP v = reinterpret_cast<const TP *>(rp)[a < k ? a : k - 1];
+                dst[w] = (ok_e && a < k) ? v : TP{};
+            }
+        }
+    };
+    bool bad = false;
+    // Forming the slab rows of one step: (0) z partial sums, (1) z over the
+    // four lanes and u, (2, 3) the two halves of the row writes.
+    double zr, zi, ur, ui;
+    auto form = [&](int part, const TP (&src)[WPT], double *Xs, bool valid) {
+        if (part == 0) {
+            zr = 0.0;
+            zi = 0.0;
+#pragma unroll
+            for (int w = 0; w < WPT; ++w) {
+                const double ar = (double)src[w].x, ai = (double)src[w].y;
+                double wr, wi;
+                if constexpr (V_LDS) {
+                    const int a = 4 * w + sub;
+                    wr = vs[2 * a];
+                    wi = vs[2 * a + 1];
+                } else {
+                    wr = vr[w];
+                    wi = vi[w];
+                }
+                zr = fma(wr, ar, fma(-wi, ai, zr));
+                zi = fma(wr, ai, fma(wi, ar, zi));
+            }
+        } else if (part == 1) {
+            zr += quad_swap<0xB1>(zr);
+            zi += quad_swap<0xB1>(zi);
+            zr += quad_swap<0x4E>(zr);
+            zi += quad_swap<0x4E>(zi);
+            const double I = zr * zr + zi * zi;
+            ur = 0.0;
+            ui = 0.0;
+            if (valid) {
+                if (I > 0.0 && isfinite(I)) {
+                    const double rI = 1.0 / I;          // 1 / z = conj(z) / I
+                    ur = zr * rI;
+                    ui = -zi * rI;
+                } else {
+                    bad = true;
+                }
+            }
+        } else {
+            double *xw = Xs + wofs;
+            constexpr int H = (WPT + 1) / 2;
+#pragma unroll
+            for (int w = part == 2 ? 0 : H; w < (part == 2 ? H : WPT); ++w) {
+                const double ar = (double)src[w].x, ai = (double)src[w].y;
+                xw[4 * w] = fma(ar, ur, -ai * ui);              // Re (A u), column 4 w + sub
+                xw[KP + 4 * w] = fma(ar, ui, ai * ur);          // Im (A u)
+            }
+        }
+    };
+    auto slab_fence = [] {
+        // LDS operations of one wave complete in order; the fences keep the compiler's
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    // one step: form the step's rows (the next step's loads in flight), then its MFMAs
+    auto step = [&](const TP (&cur)[WPT], TP (&nxt)[WPT], int64_t b) {
+        const bool valid = b + row < r1;
+        form(0, cur, X, valid);
+        form(1, cur, X, valid);
+        slab_fence();                                   // the previous step's reads come first
+        form(2, cur, X, valid);
+        form(3, cur, X, valid);
+        fetch(nxt, b + STEP + row);
+        __builtin_amdgcn_sched_barrier(0);              // the loads stay ahead of the MFMAs
+        slab_fence();
+        const double *xm = X + mofs;
+#pragma unroll
+        for (int ks = 0; ks < kHRows / 4; ++ks) {
+            double colv[NT];
+#pragma unroll
+            for (int c = 0; c < NT; ++c) colv[c] = xm[4 * ks * XS + 4 * (ks & 1) + 16 * c];
+            mfma_tiles<NT, T0>(acc, colv, std::make_integer_sequence<int, NTL>{});
+        }
+    };
+    // two steps per trip so that the two register buffers swap by name
+    TP b0[WPT], b1[WPT];
+    int64_t base = r0 + kHRows * wave;
+    fetch(b0, base + row);
+    for (; base < r1; base += 2 * STEP) {
+        step(b0, b1, base);
+        if (base + STEP >= r1) break;
+        step(b1, b0, base + STEP);
+    }
+    if (bad) atomicOr(flag, 1u);
+    // tile sums in wave order; item j of lane l is row l / 16 + 4 j, column l % 16
+    double *Gs = lds;
+#pragma unroll
+    for (int w = 0; w < kHWaves; ++w) {
+        __syncthreads();
+        if (wave == w) {
+#pragma unroll
+            for (int i = 0; i < NTL; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    double &g = Gs[i * 256 + (er + 4 * j) * 16 + ec];
+                    g = w == 0 ? acc[i][j] : g + acc[i][j];
+                }
+        }
+    }
     __syncthreads();
-    if (tid == 0) {
-        double s = 0.0;                        // S = Re sum_a conj(V_a) (M V)_a
-        for (int a = 0; a < k; ++a) s = fma(V[2 * a], mv[2 * a], fma(V[2 * a + 1], mv[2 * a + 1], s));
-        s_S = s;
+    double *out = partials + (int64_t)blockIdx.x * ntu * 256 + T0 * 256;
+    for (int idx = tid; idx < NTL * 256; idx += kHThreads) out[idx] = Gs[idx];
+}
+
+// First-level sum: p1[c][e] = sum of the block partials c * kHChunk .. in block order.
+__global__ __launch_bounds__(64) void hess_chunk_kernel(const double *__restrict__ partials, int nblocks,
+                                                        int entries, double *__restrict__ p1) {
+    const int e = blockIdx.x * 64 + threadIdx.x, c = blockIdx.y;
+    if (e >= entries) return;
+    const int b0 = c * kHChunk, b1 = b0 + kHChunk < nblocks ? b0 + kHChunk : nblocks;
+    double s = 0.0;
+#pragma unroll 8
+    for (int b = b0; b < b1; ++b) s += partials[(int64_t)b * entries + e];
+    p1[(int64_t)c * entries + e] = s;
+}
+
+// Second level: G[e] = sum over the chunks, one 64-lane block per entry, fixed-order tree.
+__global__ __launch_bounds__(64) void hess_finish_kernel(const double *__restrict__ p1, int nchunks, int entries,
+                                                         double *__restrict__ Gm) {
+    const int e = blockIdx.x;
+    double s = 0.0;
+    for (int c = threadIdx.x; c < nchunks; c += 64) s += p1[(int64_t)c * entries + e];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+    if (threadIdx.x == 0) Gm[e] = s;
+}
+
+// G[r][c] from the tile-major upper triangle (NT column blocks).
+__device__ __forceinline__ double g_at(const double *Gm, int nt, int r, int c) {
+    if ((r >> 4) > (c >> 4)) {
+        const int t = r;
+        r = c;
+        c = t;
+    }
+    const int p = r >> 4, q = c >> 4;
+    const int tile = p * nt - p * (p - 1) / 2 + (q - p);
+    return Gm[tile * 256 + (r & 15) * 16 + (c & 15)];
+}
+
+// H (2k x 2k, row-major) from G, M and M V; H[2k * 2k] = status flags.
+__global__ __launch_bounds__(256) void hess_assemble_kernel(const double *__restrict__ Gm, int kp,
+                                                            const double *__restrict__ M,
+                                                            const double *__restrict__ mv,
+                                                            const double *__restrict__ V, int k, double nd,
+                                                            int extended, const unsigned *__restrict__ flag,
+                                                            double *__restrict__ H) {
+    __shared__ double s_S;
+    const int tid = threadIdx.x, n2 = 2 * k;
+    if (tid < 64) {                                     // S = Re sum_a conj(V_a) (M V)_a
+        double s = tid < k ? fma(V[2 * tid], mv[2 * tid], V[2 * tid + 1] * mv[2 * tid + 1]) : 0.0;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+        if (tid == 0) s_S = s;
     }
     __syncthreads();
     const double S = s_S;
-    for (int idx = tid; idx < n2 * n2; idx += blockDim.x) {
-        const int m = idx / n2, n = idx % n2;
-        const int a = m >> 1, c = n >> 1, pa = m & 1, pc = n & 1;
+    const int nt = kp / 8;
+    const int idx = blockIdx.x * 256 + tid;
+    if (idx < n2 * n2) {
+        const int m = idx / n2, nn = idx % n2;
+        const int a = m >> 1, c = nn >> 1, pa = m & 1, pc = nn & 1;
         // Re T = Grr - Gii, Im T = Gri + Gri^T
-        const int nc = 2 * kp;
-        const double tr = Gm[a * nc + c] - Gm[(kp + a) * nc + kp + c];
-        const double ti = Gm[a * nc + kp + c] + Gm[(kp + a) * nc + c];
-        const double mr = M[2 * (a * k + c)], mi = M[2 * (a * k + c) + 1];
+        const double tr = g_at(Gm, nt, a, c) - g_at(Gm, nt, kp + a, kp + c);
+        const double ti = g_at(Gm, nt, a, kp + c) + g_at(Gm, nt, kp + a, c);
+        const double mr = M ? M[2 * (a * k + c)] : 0.0, mi = M ? M[2 * (a * k + c) + 1] : 0.0;
         // block entries of d2(sum ln I) and d2S for (x or y of a, x or y of c)
         double hl, d2s;
-        if (!pa && !pc) { hl = -2.0 * tr; d2s = 2.0 * mr; }
-        else if (!pa && pc) { hl = 2.0 * ti; d2s = -2.0 * mi; }
-        else if (pa && !pc) { hl = 2.0 * ti; d2s = 2.0 * mi; }
-        else { hl = 2.0 * tr; d2s = 2.0 * mr; }
+        if (!pa && !pc) {
+            hl = -2.0 * tr;
+            d2s = 2.0 * mr;
+        } else if (!pa && pc) {
+            hl = 2.0 * ti;
+            d2s = -2.0 * mi;
+        } else if (pa && !pc) {
+            hl = 2.0 * ti;
+            d2s = 2.0 * mi;
+        } else {
+            hl = 2.0 * tr;
+            d2s = 2.0 * mr;
+        }
         double h;
         if (extended) {
             h = -hl + d2s;
         } else if (nd == 0.0) {
             h = 0.0;
         } else {
-            const double dsm = 2.0 * mv[m], dsn = 2.0 * mv[n];     // dS: (2 Re MV, 2 Im MV) interleaved
+            const double dsm = 2.0 * mv[m], dsn = 2.0 * mv[nn];     // dS: (2 Re MV, 2 Im MV) interleaved
             h = -hl + nd * (d2s / S - dsm * dsn / (S * S));
         }
         H[idx] = h;
     }
-    if (tid == 0) {
+    if (blockIdx.x == 0 && tid == 0) {
         const bool dom = (*flag != 0u) || (!extended && nd > 0.0 && !(S > 0.0));
         H[n2 * n2] = dom ? 1.0 : 0.0;
     }
 }
 
-}  // namespace
-
-int hessian_kp(int k) { return 8 * ((k + 7) / 8); }
-size_t hessian_g_doubles(int k) { return (size_t)(2 * hessian_kp(k)) * (size_t)(2 * hessian_kp(k)); }
-size_t hessian_partial_doubles(int k, int blocks) { return (size_t)blocks * hessian_g_doubles(k); }
-
-template <typename T>
-hipError_t launch_hess_mfma(const T *A, int64_t n, int64_t ld, int k, const double *V, double *partials,
-                            unsigned *flag, int blocks, hipStream_t s) {
-    switch (hessian_kp(k)) {
-#define PWA_HESS_CASE(KP_)                                                                                   \
-    case KP_:                                                                                                \
-        hipLaunchKernelGGL((hess_mfma_kernel<T, KP_>), dim3(blocks), dim3(kHThreads), 0, s, A, n, ld, k, V, \
-                           partials, flag);                                                                  \
-        break;
-        PWA_HESS_CASE(8) PWA_HESS_CASE(16) PWA_HESS_CASE(24) PWA_HESS_CASE(32)
-        PWA_HESS_CASE(40) PWA_HESS_CASE(48) PWA_HESS_CASE(56) PWA_HESS_CASE(64)
-#undef PWA_HESS_CASE
-        default: return hipErrorInvalidValue;
-    }
+template <typename T, int KP, int G>
+hipError_t launch_group(const T *A, int64_t n, int64_t ld, int k, const double *V, double *partials,
+                        unsigned *flag, int blocks, hipStream_t s) {
+    constexpr int NT = KP / 8, NTU = tile_count(NT), NG = tile_groups(NT), NTLM = (NTU + NG - 1) / NG;
+    constexpr int T0 = G * NTLM, NTL = NTU - T0 < NTLM ? NTU - T0 : NTLM;
+    hipLaunchKernelGGL((hess_mfma_kernel<T, KP, T0, NTL>), dim3(blocks), dim3(kHThreads), 0, s, A, n, ld, k, V, NTU,
+                       partials, flag);
     return hipGetLastError();
 }
 
+template <typename T, int KP, int... G>
+hipError_t launch_groups(const T *A, int64_t n, int64_t ld, int k, const double *V, double *partials,
+                         unsigned *flag, int blocks, hipStream_t s, std::integer_sequence<int, G...>) {
+    hipError_t e = hipSuccess;
+    ((e = e == hipSuccess ? launch_group<T, KP, G>(A, n, ld, k, V, partials, flag, blocks, s) : e), ...);
+    return e;
+}
+
+template <typename T, int KP>
+hipError_t launch_pass(const T *A, int64_t n, int64_t ld, int k, const double *V, double *partials, unsigned *flag,
+                       int blocks, hipStream_t s) {
+    return launch_groups<T, KP>(A, n, ld, k, V, partials, flag, blocks, s,
+                                std::make_integer_sequence<int, tile_groups(KP / 8)>{});
+}
+
+// Resident blocks per CU of the first tile group's kernel.
+template <typename T, int KP>
+int pass_occupancy() {
+    constexpr int NT = KP / 8, NTU = tile_count(NT), NG = tile_groups(NT), NTLM = (NTU + NG - 1) / NG;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, hess_mfma_kernel<T, KP, 0, NTLM>, kHThreads, 0) !=
+        hipSuccess)
+        nb = 1;
+    return nb > 0 ? nb : 1;
+}
+
+template <typename T>
+int occupancy(int kp) {
+    switch (kp) {
+        case 8: return pass_occupancy<T, 8>();
+        case 16: return pass_occupancy<T, 16>();
+        case 24: return pass_occupancy<T, 24>();
+        case 32: return pass_occupancy<T, 32>();
+        case 40: return pass_occupancy<T, 40>();
+        case 48: return pass_occupancy<T, 48>();
+        case 56: return pass_occupancy<T, 56>();
+        default: return pass_occupancy<T, 64>();
+    }
+}
+
+template <typename T>
+hipError_t launch_data_pass(const T *A, int64_t n, int64_t ld, int k, const double *V, double *partials,
+                            unsigned *flag, int blocks, hipStream_t s) {
+    switch (8 * ((k + 7) / 8)) {
+        case 8: return launch_pass<T, 8>(A, n, ld, k, V, partials, flag, blocks, s);
+        case 16: return launch_pass<T, 16>(A, n, ld, k, V, partials, flag, blocks, s);
+        case 24: return launch_pass<T, 24>(A, n, ld, k, V, partials, flag, blocks, s);
+        case 32: return launch_pass<T, 32>(A, n, ld, k, V, partials, flag, blocks, s);
+        case 40: return launch_pass<T, 40>(A, n, ld, k, V, partials, flag, blocks, s);
+        case 48: return launch_pass<T, 48>(A, n, ld, k, V, partials, flag, blocks, s);
+        case 56: return launch_pass<T, 56>(A, n, ld, k, V, partials, flag, blocks, s);
+        case 64: return launch_pass<T, 64>(A, n, ld, k, V, partials, flag, blocks, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int hess_kp(int k) { return 8 * ((k + 7) / 8); }
+size_t hess_entries(int k) { return (size_t)tile_count(hess_kp(k) / 8) * 256; }
+int hess_chunks(int blocks) { return (blocks + kHChunk - 1) / kHChunk; }
+
+}  // namespace
+
+int hessian_blocks(pwa_prec prec, int k, int cu_count, int64_t n) {
+    if (k < 1 || k > PWA_MAX_K) return 1;
+    const int kp = hess_kp(k);
+    const int occ = prec == PWA_F32 ? occupancy<float>(kp) : occupancy<double>(kp);
+    const int64_t want = (int64_t)cu_count * occ, need = (n + kHWaves * kHRows - 1) / (kHWaves * kHRows);
+    return (int)std::max<int64_t>(1, std::min(want, need));
+}
+
+size_t hessian_work_doubles(int k, int blocks) {
+    const size_t entries = hess_entries(k);
+    return (size_t)blocks * entries + (size_t)hess_chunks(blocks) * entries + entries + 2 * (size_t)k;
+}
+
 hipError_t launch_hessian(pwa_prec prec, const void *A, int64_t n, int64_t ld, int k, const double *V_dev,
-                          const double *M, double nd, int extended, double *partials, int blocks, double *Gm,
-                          unsigned *flag, double *H, hipStream_t stream) {
+                          const double *M, double nd, int extended, double *work, int blocks, unsigned *flag,
+                          double *H, hipStream_t stream) {
     if (k < 1 || k > PWA_MAX_K || blocks < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(hess_clear_kernel, dim3(1), dim3(1), 0, stream, flag);
+    const int entries = (int)hess_entries(k);
+    double *partials = work;
+    double *p1 = partials + (size_t)blocks * entries;
+    double *Gm = p1 + (size_t)hess_chunks(blocks) * entries;
+    double *mv = Gm + entries;
+    hipLaunchKernelGGL(hess_prologue_kernel, dim3(k), dim3(64), 0, stream, M, V_dev, k, mv, flag);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    int nch = 0;
     if (n > 0) {
         e = prec == PWA_F32
-                ? launch_hess_mfma(static_cast<const float *>(A), n, ld, k, V_dev, partials, flag, blocks, stream)
-                : launch_hess_mfma(static_cast<const double *>(A), n, ld, k, V_dev, partials, flag, blocks, stream);
+                ? launch_data_pass(static_cast<const float *>(A), n, ld, k, V_dev, partials, flag, blocks, stream)
+                : launch_data_pass(static_cast<const double *>(A), n, ld, k, V_dev, partials, flag, blocks, stream);
         if (e != hipSuccess) return e;
-    } else {
-        blocks = 0;
+        nch = hess_chunks(blocks);
+        hipLaunchKernelGGL(hess_chunk_kernel, dim3((entries + 63) / 64, nch), dim3(64), 0, stream, partials, blocks,
+                           entries, p1);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    const int entries = (int)hessian_g_doubles(k);
-    hipLaunchKernelGGL(hess_finish_kernel, dim3(entries), dim3(kFinThreads), 0, stream, partials, blocks, entries, Gm);
+    hipLaunchKernelGGL(hess_finish_kernel, dim3(entries), dim3(64), 0, stream, p1, nch, entries, Gm);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(hess_assemble_kernel, dim3(1), dim3(256), 0, stream, Gm, hessian_kp(k), M, V_dev, k, nd,
-                       extended, flag, H);
+    hipLaunchKernelGGL(hess_assemble_kernel, dim3((4 * k * k + 255) / 256), dim3(256), 0, stream, Gm, hess_kp(k), M,
+                       mv, V_dev, k, nd, extended, flag, H);
     return hipGetLastError();
 }
 

@@ -243,16 +243,16 @@ size_t gram_partial_doubles(int k, int blocks);
 
 // Hessian of the NLL in the real parameters (hessian.hip): one pass over the n
 // data rows (A, row stride ld complex) at V_dev (2k doubles, device) with the
-// MC matrix M (k x k complex, FP64, 1/N_gen folded in), nd data events and the
-// likelihood form; writes H (2k x 2k row-major, then one status double: 0 ok,
-// 1 domain failure).  partials: hessian_partial_doubles(k, blocks) doubles;
-// Gm: hessian_g_doubles(k) doubles (the summed real 2 kp x 2 kp matrix G of
-// the pass, kp = k rounded up to a multiple of 8); flag: one unsigned.
+// MC matrix M (k x k complex, FP64, 1/N_gen folded in; null when the
+// likelihood has no normalisation term), nd data events and the likelihood
+// form; writes H (2k x 2k row-major, then one status double: 0 ok, 1 domain
+// failure).  blocks: hessian_blocks(prec, k, cu_count, n); work:
+// hessian_work_doubles(k, blocks) doubles; flag: one unsigned.
 hipError_t launch_hessian(pwa_prec prec, const void *A, int64_t n, int64_t ld, int k, const double *V_dev,
-                          const double *M, double nd, int extended, double *partials, int blocks, double *Gm,
-                          unsigned *flag, double *H, hipStream_t stream);
-size_t hessian_partial_doubles(int k, int blocks);
-size_t hessian_g_doubles(int k);
+                          const double *M, double nd, int extended, double *work, int blocks, unsigned *flag,
+                          double *H, hipStream_t stream);
+int hessian_blocks(pwa_prec prec, int k, int cu_count, int64_t n);
+size_t hessian_work_doubles(int k, int blocks);
 
 // ---------------------------------------------------------------- surrogate MLP
 // Device buffers of the in -> hidden -> hidden -> 1 network (FP32 master
