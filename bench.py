@@ -436,7 +436,9 @@ def extra_hessian(ctx, V, nd: int, k: int, reps: int = 20):
                          "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFS, "traffic": None,
                          "kernel": "hess_mfma_kernel (FP64 MFMA data pass) + partial sums + assembly",
                          "alg_flops_per_call": alg_flops,
-                         "note": "kernels of one call (HIP events), without the V upload and H readback"}}
+                         "note": "events before the first and after the last kernel of one synchronous call "
+                                 "(data pass, partial sums, assembly of H); includes the wait for the first "
+                                 "launch on the idle stream"}}
 
 
 def extra_hessian_k48(nd: int = 1_000_000, nm: int = 200_000):

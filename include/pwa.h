@@ -314,8 +314,10 @@ pwa_status pwa_kernel_time(pwa_ctx *ctx, double *avg_ms, int64_t *count);
  * per-vector combine kernel. */
 pwa_status pwa_batch_kernel_time(pwa_ctx *ctx, double *avg_ms, int64_t *count);
 
-/* Same for pwa_hessian: all of its kernels (the data pass and the sums and
- * assembly after it), without the V upload and the H readback. */
+/* Same for pwa_hessian: events recorded on the context's stream before its
+ * first kernel and after its last (the data pass, the partial sums and the
+ * assembly of H), without the H readback.  A synchronous call starts on an
+ * idle stream, so the interval includes the wait for the first launch. */
 pwa_status pwa_hessian_kernel_time(pwa_ctx *ctx, double *avg_ms, int64_t *count);
 
 /* ------------------------------------------------------------------------

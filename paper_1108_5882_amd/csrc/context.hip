@@ -79,6 +79,8 @@ struct pwa_ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> batch_events;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> hess_events;
+    bool hess_clean = false;   // the Hessian's status word and counters rest at zero
+    int hess_layout[2] = {0, 0};   // (k, blocks) of the work layout they were zeroed for
     std::vector<hipEvent_t> event_pool;   // timing events kept for reuse
 
     // batched (many-V) path: per-wave FP16 scales of the amplitudes, device scratch
@@ -997,14 +999,16 @@ pwa_status pwa_hessian(pwa_ctx *ctx, const double *V, double *H) {
     pwa_status st;
     if (need_mc && (st = ensure_gram(ctx)) != PWA_OK) return st;
     const int blocks = hessian_blocks(ctx->prec, k, ctx->cu_count, nd);
-    const size_t n_work = hessian_work_doubles(k, blocks), n_v = 2 * (size_t)k, n_h = 4 * (size_t)k * k + 1;
-    const size_t doubles = n_work + n_v + n_h + 1;
+    const size_t n_work = hessian_work_doubles(k, blocks), n_h = 4 * (size_t)k * k + 1;
+    const size_t doubles = n_work + n_h + 1;
+    const size_t cap0 = ctx->h_cap;
     if ((st = grow(ctx, &ctx->h_buf, &ctx->h_cap, sizeof(double) * doubles, "hipMalloc(hessian)"))) return st;
+    if (ctx->h_cap != cap0 || ctx->hess_layout[0] != k || ctx->hess_layout[1] != blocks) ctx->hess_clean = false;
+    ctx->hess_layout[0] = k;
+    ctx->hess_layout[1] = blocks;
     double *work = static_cast<double *>(ctx->h_buf);
-    double *Vd = work + n_work, *Hd = Vd + n_v;
+    double *Hd = work + n_work;
     unsigned *flag = reinterpret_cast<unsigned *>(Hd + n_h);
-    PWA_HIP(ctx, hipMemcpyAsync(Vd, V, sizeof(double) * n_v, hipMemcpyHostToDevice, ctx->stream),
-            "hipMemcpyAsync(V)");
     // without MC rows (Eq. 2 form, no data) there is no normalisation term
     const double *M = need_mc ? ctx->gram : nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1017,14 +1021,17 @@ pwa_status pwa_hessian(pwa_ctx *ctx, const double *V, double *H) {
         ctx->hess_events.emplace_back(e0, e1);
         PWA_HIP(ctx, hipEventRecord(e0, ctx->stream), "hipEventRecord");
     }
-    hipError_t e = launch_hessian(ctx->prec, ctx->s[0].A, nd, ctx->ld, k, Vd, M, (double)nd, ctx->extended, work,
-                                  blocks, flag, Hd, ctx->stream);
+    const bool clear = !ctx->hess_clean;
+    ctx->hess_clean = false;
+    hipError_t e = launch_hessian(ctx->prec, ctx->s[0].A, nd, ctx->ld, k, V, M, (double)nd, ctx->extended, work,
+                                  blocks, clear, flag, Hd, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "hessian launch");
     if (ctx->timing) PWA_HIP(ctx, hipEventRecord(e1, ctx->stream), "hipEventRecord");
     std::vector<double> h(n_h);
     PWA_HIP(ctx, hipMemcpyAsync(h.data(), Hd, sizeof(double) * n_h, hipMemcpyDeviceToHost, ctx->stream),
             "hipMemcpyAsync(H)");
     PWA_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    ctx->hess_clean = true;
     std::copy(h.begin(), h.end() - 1, H);
     ctx->last_flags = h.back() != 0.0 ? 1u : 0u;
     return ctx->last_flags ? fail(ctx, PWA_E_DOMAIN, "zero coherent sum or non-positive normalisation") : PWA_OK;

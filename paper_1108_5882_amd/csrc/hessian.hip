@@ -13,11 +13,13 @@
 //   Eq. 2 form:  H = -d2(sum ln I) + N_D (d2S / S - dS dS^T / S^2)
 //   Eq. 3 form:  H = -d2(sum ln I) + d2S
 //
-// Launches: a prologue (status word, M V), the data pass on the FP64 matrix
-// cores (hess_mfma_kernel, one launch per group of at most 21 output tiles),
-// a two-level fixed-order sum of the block partials, and the assembly of H.
+// Launches: the data pass on the FP64 matrix cores (hess_mfma_kernel, one
+// launch per group of at most 21 output tiles), the fixed-order sum of its
+// block partials (hess_sum_kernel) and the assembly of H.
+#include <atomic>
 #include <utility>
 
+#include "block_reduce.hpp"
 #include "internal.hpp"
 
 namespace pwa {
@@ -74,6 +76,11 @@ __device__ __forceinline__ double quad_swap(double x) {
     return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
+// V by value in the kernel arguments (no upload before the launches).
+struct HessV {
+    double v[2 * PWA_MAX_K];
+};
+
 template <typename T> struct Pair;
 template <> struct Pair<float> { typedef float v __attribute__((ext_vector_type(2))); };
 template <> struct Pair<double> { typedef double v __attribute__((ext_vector_type(2))); };
@@ -86,30 +93,6 @@ __device__ __forceinline__ void mfma_tiles(d4 *acc, const double *colv, std::int
                                                     colv[std::integral_constant<int, tile_q(T0 + I, NT)>::value],
                                                     acc[I], 0, 0, 0)),
      ...);
-}
-
-// Prologue: status word and (M V)_a, one wave per wave index a (M may be null:
-// no normalisation term).
-__global__ __launch_bounds__(64) void hess_prologue_kernel(const double *__restrict__ M,
-                                                           const double *__restrict__ V, int k,
-                                                           double *__restrict__ mv, unsigned *__restrict__ flag) {
-    const int a = blockIdx.x, c = threadIdx.x;
-    if (a == 0 && c == 0) *flag = 0u;
-    double re = 0.0, im = 0.0;
-    if (M && c < k) {
-        const double mr = M[2 * (a * k + c)], mi = M[2 * (a * k + c) + 1];
-        re = fma(mr, V[2 * c], -mi * V[2 * c + 1]);
-        im = fma(mr, V[2 * c + 1], mi * V[2 * c]);
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        re += __shfl_xor(re, off);
-        im += __shfl_xor(im, off);
-    }
-    if (c == 0) {
-        mv[2 * a] = re;
-        mv[2 * a + 1] = im;
-    }
 }
 
 // Data pass on the FP64 matrix cores.  With u_i = 1 / z_i and B_i = A_i u_i
@@ -130,7 +113,7 @@ __global__ __launch_bounds__(64) void hess_prologue_kernel(const double *__restr
 // symmetric contraction plus about 14 K for z, u and B.
 template <typename T, int KP, int T0, int NTL>
 __global__ __launch_bounds__(kHThreads) void hess_mfma_kernel(const T *__restrict__ A, int64_t n, int64_t ld, int k,
-                                                              const double *__restrict__ V, int ntu,
+                                                              const HessV V, int ntu,
                                                               double *__restrict__ partials,
                                                               unsigned *__restrict__ flag) {
     constexpr int NC = 2 * KP;
@@ -159,14 +142,14 @@ __global__ __launch_bounds__(kHThreads) void hess_mfma_kernel(const T *__restric
 
     double vr[V_LDS ? 1 : WPT], vi[V_LDS ? 1 : WPT];
     if constexpr (V_LDS) {
-        for (int i = tid; i < 2 * KP; i += kHThreads) vs[i] = i < 2 * k ? V[i] : 0.0;
+        for (int i = tid; i < 2 * KP; i += kHThreads) vs[i] = i < 2 * k ? V.v[i] : 0.0;
         __syncthreads();
     } else {
 #pragma unroll
         for (int w = 0; w < WPT; ++w) {
             const int a = 4 * w + sub;
-            vr[w] = a < k ? V[2 * a] : 0.0;
-            vi[w] = a < k ? V[2 * a + 1] : 0.0;
+            vr[w] = a < k ? V.v[2 * a] : 0.0;
+            vi[w] = a < k ? V.v[2 * a + 1] : 0.0;
         }
     }
     d4 acc[NTL];
@@ -303,27 +286,42 @@ __global__ __launch_bounds__(kHThreads) void hess_mfma_kernel(const T *__restric
     for (int idx = tid; idx < NTL * 256; idx += kHThreads) out[idx] = Gs[idx];
 }
 
-// First-level sum: p1[c][e] = sum of the block partials c * kHChunk .. in block order.
-__global__ __launch_bounds__(64) void hess_chunk_kernel(const double *__restrict__ partials, int nblocks,
-                                                        int entries, double *__restrict__ p1) {
-    const int e = blockIdx.x * 64 + threadIdx.x, c = blockIdx.y;
-    if (e >= entries) return;
-    const int b0 = c * kHChunk, b1 = b0 + kHChunk < nblocks ? b0 + kHChunk : nblocks;
-    double s = 0.0;
+// Sum of the block partials in two fixed-order levels within one launch:
+// block (x, y) adds the partials of blocks y * kHChunk .. for its 64 entries
+// in block order into p1[y]; the last of column x's blocks to arrive (arrival
+// counter, which it resets) adds p1[0 ..) in chunk order into G.  p1 crosses
+// blocks, so it is stored and loaded as device-scope atomics, and each block
+// waits for its stores before it announces them.
+__global__ __launch_bounds__(64) void hess_sum_kernel(const double *__restrict__ partials, int nblocks, int entries,
+                                                      double *__restrict__ p1, unsigned *__restrict__ counters,
+                                                      double *__restrict__ Gm) {
+    __shared__ unsigned s_last;
+    const int e = blockIdx.x * 64 + threadIdx.x, c = blockIdx.y, nch = gridDim.y;
+    if (e < entries) {
+        const int b0 = c * kHChunk, b1 = b0 + kHChunk < nblocks ? b0 + kHChunk : nblocks;
+        double sum = 0.0;
 #pragma unroll 8
-    for (int b = b0; b < b1; ++b) s += partials[(int64_t)b * entries + e];
-    p1[(int64_t)c * entries + e] = s;
-}
-
-// Second level: G[e] = sum over the chunks, one 64-lane block per entry, fixed-order tree.
-__global__ __launch_bounds__(64) void hess_finish_kernel(const double *__restrict__ p1, int nchunks, int entries,
-                                                         double *__restrict__ Gm) {
-    const int e = blockIdx.x;
-    double s = 0.0;
-    for (int c = threadIdx.x; c < nchunks; c += 64) s += p1[(int64_t)c * entries + e];
+        for (int b = b0; b < b1; ++b) sum += partials[(int64_t)b * entries + e];
+        st_dev(p1 + (int64_t)c * entries + e, sum);
+    }
+    wait_stores();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(&counters[blockIdx.x], 1u) == (unsigned)(nch - 1);
+    __syncthreads();
+    if (!s_last) return;
+    if (threadIdx.x == 0) __hip_atomic_store(&counters[blockIdx.x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (e < entries) {
+        double sum = 0.0;
+        for (int c0 = 0; c0 < nch; c0 += 16) {
+            double v[16];
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
-    if (threadIdx.x == 0) Gm[e] = s;
+            for (int u = 0; u < 16; ++u)
+                v[u] = c0 + u < nch ? ld_dev(p1 + (int64_t)(c0 + u) * entries + e) : 0.0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) sum += v[u];
+        }
+        Gm[e] = sum;
+    }
 }
 
 // G[r][c] from the tile-major upper triangle (NT column blocks).
@@ -338,20 +336,41 @@ __device__ __forceinline__ double g_at(const double *Gm, int nt, int r, int c) {
     return Gm[tile * 256 + (r & 15) * 16 + (c & 15)];
 }
 
-// H (2k x 2k, row-major) from G, M and M V; H[2k * 2k] = status flags.
+// H (2k x 2k, row-major) from G, M and V; H[2k * 2k] = status flags.  Every
+// block forms M V (four threads per wave index, lane-order sums) and S; block
+// 0 reads the status word of the data pass and clears it for the next call.
 __global__ __launch_bounds__(256) void hess_assemble_kernel(const double *__restrict__ Gm, int kp,
                                                             const double *__restrict__ M,
-                                                            const double *__restrict__ mv,
-                                                            const double *__restrict__ V, int k, double nd,
-                                                            int extended, const unsigned *__restrict__ flag,
+                                                            const HessV V, int k, double nd,
+                                                            int extended, unsigned *__restrict__ flag,
                                                             double *__restrict__ H) {
+    __shared__ double mv[2 * PWA_MAX_K];
     __shared__ double s_S;
     const int tid = threadIdx.x, n2 = 2 * k;
+    {
+        const int a = tid >> 2, q = tid & 3;
+        double re = 0.0, im = 0.0;
+        if (M && a < k)
+            for (int c = q; c < k; c += 4) {
+                const double mr = M[2 * (a * k + c)], mi = M[2 * (a * k + c) + 1];
+                re = fma(mr, V.v[2 * c], fma(-mi, V.v[2 * c + 1], re));
+                im = fma(mr, V.v[2 * c + 1], fma(mi, V.v[2 * c], im));
+            }
+        re += quad_swap<0xB1>(re);
+        im += quad_swap<0xB1>(im);
+        re += quad_swap<0x4E>(re);
+        im += quad_swap<0x4E>(im);
+        if (q == 0 && a < k) {
+            mv[2 * a] = re;
+            mv[2 * a + 1] = im;
+        }
+    }
+    __syncthreads();
     if (tid < 64) {                                     // S = Re sum_a conj(V_a) (M V)_a
-        double s = tid < k ? fma(V[2 * tid], mv[2 * tid], V[2 * tid + 1] * mv[2 * tid + 1]) : 0.0;
+        double sv = tid < k ? fma(V.v[2 * tid], mv[2 * tid], V.v[2 * tid + 1] * mv[2 * tid + 1]) : 0.0;
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
-        if (tid == 0) s_S = s;
+        for (int off = 32; off >= 1; off >>= 1) sv += __shfl_xor(sv, off);
+        if (tid == 0) s_S = sv;
     }
     __syncthreads();
     const double S = s_S;
@@ -393,11 +412,12 @@ __global__ __launch_bounds__(256) void hess_assemble_kernel(const double *__rest
     if (blockIdx.x == 0 && tid == 0) {
         const bool dom = (*flag != 0u) || (!extended && nd > 0.0 && !(S > 0.0));
         H[n2 * n2] = dom ? 1.0 : 0.0;
+        *flag = 0u;
     }
 }
 
 template <typename T, int KP, int G>
-hipError_t launch_group(const T *A, int64_t n, int64_t ld, int k, const double *V, double *partials,
+hipError_t launch_group(const T *A, int64_t n, int64_t ld, int k, const HessV &V, double *partials,
                         unsigned *flag, int blocks, hipStream_t s) {
     constexpr int NT = KP / 8, NTU = tile_count(NT), NG = tile_groups(NT), NTLM = (NTU + NG - 1) / NG;
     constexpr int T0 = G * NTLM, NTL = NTU - T0 < NTLM ? NTU - T0 : NTLM;
@@ -407,7 +427,7 @@ hipError_t launch_group(const T *A, int64_t n, int64_t ld, int k, const double *
 }
 
 template <typename T, int KP, int... G>
-hipError_t launch_groups(const T *A, int64_t n, int64_t ld, int k, const double *V, double *partials,
+hipError_t launch_groups(const T *A, int64_t n, int64_t ld, int k, const HessV &V, double *partials,
                          unsigned *flag, int blocks, hipStream_t s, std::integer_sequence<int, G...>) {
     hipError_t e = hipSuccess;
     ((e = e == hipSuccess ? launch_group<T, KP, G>(A, n, ld, k, V, partials, flag, blocks, s) : e), ...);
@@ -415,7 +435,7 @@ hipError_t launch_groups(const T *A, int64_t n, int64_t ld, int k, const double 
 }
 
 template <typename T, int KP>
-hipError_t launch_pass(const T *A, int64_t n, int64_t ld, int k, const double *V, double *partials, unsigned *flag,
+hipError_t launch_pass(const T *A, int64_t n, int64_t ld, int k, const HessV &V, double *partials, unsigned *flag,
                        int blocks, hipStream_t s) {
     return launch_groups<T, KP>(A, n, ld, k, V, partials, flag, blocks, s,
                                 std::make_integer_sequence<int, tile_groups(KP / 8)>{});
@@ -447,7 +467,7 @@ int occupancy(int kp) {
 }
 
 template <typename T>
-hipError_t launch_data_pass(const T *A, int64_t n, int64_t ld, int k, const double *V, double *partials,
+hipError_t launch_data_pass(const T *A, int64_t n, int64_t ld, int k, const HessV &V, double *partials,
                             unsigned *flag, int blocks, hipStream_t s) {
     switch (8 * ((k + 7) / 8)) {
         case 8: return launch_pass<T, 8>(A, n, ld, k, V, partials, flag, blocks, s);
@@ -471,43 +491,49 @@ int hess_chunks(int blocks) { return (blocks + kHChunk - 1) / kHChunk; }
 int hessian_blocks(pwa_prec prec, int k, int cu_count, int64_t n) {
     if (k < 1 || k > PWA_MAX_K) return 1;
     const int kp = hess_kp(k);
-    const int occ = prec == PWA_F32 ? occupancy<float>(kp) : occupancy<double>(kp);
+    static std::atomic<int> cache[2][PWA_MAX_K / 8 + 1];   // resident blocks per CU, 0 = not asked yet
+    std::atomic<int> &slot = cache[prec == PWA_F32 ? 0 : 1][kp / 8];
+    int occ = slot.load(std::memory_order_relaxed);
+    if (occ == 0) {
+        occ = prec == PWA_F32 ? occupancy<float>(kp) : occupancy<double>(kp);
+        slot.store(occ, std::memory_order_relaxed);
+    }
     const int64_t want = (int64_t)cu_count * occ, need = (n + kHWaves * kHRows - 1) / (kHWaves * kHRows);
     return (int)std::max<int64_t>(1, std::min(want, need));
 }
 
 size_t hessian_work_doubles(int k, int blocks) {
-    const size_t entries = hess_entries(k);
-    return (size_t)blocks * entries + (size_t)hess_chunks(blocks) * entries + entries + 2 * (size_t)k;
+    const size_t entries = hess_entries(k), cols = (entries + 63) / 64;
+    return (size_t)blocks * entries + (size_t)hess_chunks(blocks) * entries + entries + (cols + 1) / 2;
 }
 
-hipError_t launch_hessian(pwa_prec prec, const void *A, int64_t n, int64_t ld, int k, const double *V_dev,
-                          const double *M, double nd, int extended, double *work, int blocks, unsigned *flag,
-                          double *H, hipStream_t stream) {
+hipError_t launch_hessian(pwa_prec prec, const void *A, int64_t n, int64_t ld, int k, const double *V,
+                          const double *M, double nd, int extended, double *work, int blocks, bool clear,
+                          unsigned *flag, double *H, hipStream_t stream) {
     if (k < 1 || k > PWA_MAX_K || blocks < 1) return hipErrorInvalidValue;
-    const int entries = (int)hess_entries(k);
+    HessV hv{};
+    for (int i = 0; i < 2 * k; ++i) hv.v[i] = V[i];
+    const int entries = (int)hess_entries(k), cols = (entries + 63) / 64;
     double *partials = work;
     double *p1 = partials + (size_t)blocks * entries;
     double *Gm = p1 + (size_t)hess_chunks(blocks) * entries;
-    double *mv = Gm + entries;
-    hipLaunchKernelGGL(hess_prologue_kernel, dim3(k), dim3(64), 0, stream, M, V_dev, k, mv, flag);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    int nch = 0;
+    unsigned *counters = reinterpret_cast<unsigned *>(Gm + entries);
+    hipError_t e;
+    if (clear) {            // the status word and the arrival counters rest at zero between calls
+        if ((e = hipMemsetAsync(counters, 0, sizeof(unsigned) * cols, stream)) != hipSuccess) return e;
+        if ((e = hipMemsetAsync(flag, 0, sizeof(unsigned), stream)) != hipSuccess) return e;
+    }
     if (n > 0) {
         e = prec == PWA_F32
-                ? launch_data_pass(static_cast<const float *>(A), n, ld, k, V_dev, partials, flag, blocks, stream)
-                : launch_data_pass(static_cast<const double *>(A), n, ld, k, V_dev, partials, flag, blocks, stream);
+                ? launch_data_pass(static_cast<const float *>(A), n, ld, k, hv, partials, flag, blocks, stream)
+                : launch_data_pass(static_cast<const double *>(A), n, ld, k, hv, partials, flag, blocks, stream);
         if (e != hipSuccess) return e;
-        nch = hess_chunks(blocks);
-        hipLaunchKernelGGL(hess_chunk_kernel, dim3((entries + 63) / 64, nch), dim3(64), 0, stream, partials, blocks,
-                           entries, p1);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(hess_finish_kernel, dim3(entries), dim3(64), 0, stream, p1, nch, entries, Gm);
+    hipLaunchKernelGGL(hess_sum_kernel, dim3(cols, hess_chunks(blocks)), dim3(64), 0, stream, partials,
+                       n > 0 ? blocks : 0, entries, p1, counters, Gm);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(hess_assemble_kernel, dim3((4 * k * k + 255) / 256), dim3(256), 0, stream, Gm, hess_kp(k), M,
-                       mv, V_dev, k, nd, extended, flag, H);
+                       hv, k, nd, extended, flag, H);
     return hipGetLastError();
 }
 

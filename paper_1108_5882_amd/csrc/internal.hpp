@@ -242,15 +242,19 @@ hipError_t launch_gram(pwa_prec prec, const void *A, const void *w, int64_t n, i
 size_t gram_partial_doubles(int k, int blocks);
 
 // Hessian of the NLL in the real parameters (hessian.hip): one pass over the n
-// data rows (A, row stride ld complex) at V_dev (2k doubles, device) with the
+// data rows (A, row stride ld complex) at V (2k doubles, host; passed to the
+// kernels by value) with the
 // MC matrix M (k x k complex, FP64, 1/N_gen folded in; null when the
 // likelihood has no normalisation term), nd data events and the likelihood
 // form; writes H (2k x 2k row-major, then one status double: 0 ok, 1 domain
 // failure).  blocks: hessian_blocks(prec, k, cu_count, n); work:
-// hessian_work_doubles(k, blocks) doubles; flag: one unsigned.
-hipError_t launch_hessian(pwa_prec prec, const void *A, int64_t n, int64_t ld, int k, const double *V_dev,
-                          const double *M, double nd, int extended, double *work, int blocks, unsigned *flag,
-                          double *H, hipStream_t stream);
+// hessian_work_doubles(k, blocks) doubles; flag: one unsigned.  The status
+// word and the arrival counters in work are left at zero by every call that
+// completes; clear = true zeroes them first (new buffers, or after a call
+// that did not complete).
+hipError_t launch_hessian(pwa_prec prec, const void *A, int64_t n, int64_t ld, int k, const double *V,
+                          const double *M, double nd, int extended, double *work, int blocks, bool clear,
+                          unsigned *flag, double *H, hipStream_t stream);
 int hessian_blocks(pwa_prec prec, int k, int cu_count, int64_t n);
 size_t hessian_work_doubles(int k, int blocks);
 
