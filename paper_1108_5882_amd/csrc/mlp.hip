@@ -24,18 +24,93 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kGT = 256;          // GEMM block: 4 waves, 64 x 64 output tile
 constexpr int kGK = 32;           // k step (one MFMA)
-constexpr int kGS = kGK + 8;      // LDS row stride in halfs (16-byte aligned rows)
+constexpr int kGKS = 256;         // k range staged in LDS at once
+constexpr int kGS = kGKS + 8;     // LDS row stride in halfs (16-byte aligned rows)
 
 template <typename T>
 __device__ __forceinline__ float ld_f(const T *p, int64_t i) { return (float)p[i]; }
+
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_d(float x) {
+    return 0.5f * (1.f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+}
+
+// GEMM epilogues: plain store; Z = C + b (per column) stored with H = GELU(Z);
+// C * GELU'(Z) (the backward through the activation).
+enum GemmEpi { kEpiNone, kEpiBiasGelu, kEpiGeluBack };
+struct EpiArgs {
+    const float *b;
+    float *H;
+    const float *Z;
+};
+
+// dst[r][c] = fp16(src(r0 + r, s0 + c)) for the 64 rows of a tile and the
+// staged columns c < kw (zero outside the matrix or at k >= s1), where
+// src(r, k) = src[r ld + k] (TR false) or src[k ld + r] (TR true).  Four
+// consecutive elements per thread and load (16 bytes where the layout allows);
+// all loads of the stage are issued before the first LDS store.
+template <bool TR, typename T>
+__device__ __forceinline__ void gemm_stage(_Float16 *dst, const T *src, int ld, int r0, int R, int s0, int s1,
+                                           int kw, int tid) {
+    constexpr int NIT = 64 * kGKS / 4 / kGT;     // items of four elements per thread at the full stage width
+    const bool vec = sizeof(T) == 4 && ld % 4 == 0 && (reinterpret_cast<uintptr_t>(src) & 15) == 0;
+    const int per_row = kw / 4;                  // !TR: items per row; TR: 16 items per column
+    const int items = TR ? 16 * kw : 64 * per_row;
+    float4 v[NIT];
+#pragma unroll
+    for (int i = 0; i < NIT; ++i) {
+        const int it = tid + i * kGT;
+        const int r = TR ? 4 * (it % 16) : it / per_row, c = TR ? it / 16 : 4 * (it % per_row);
+        const int rr = r0 + r, k = s0 + c;
+        v[i] = float4{0.f, 0.f, 0.f, 0.f};
+        if (it >= items) continue;
+        if (!TR) {
+            if (vec && rr < R && k + 3 < s1) {
+                v[i] = *reinterpret_cast<const float4 *>(src + (int64_t)rr * ld + k);
+            } else if (rr < R) {
+                v[i].x = k < s1 ? ld_f(src, (int64_t)rr * ld + k) : 0.f;
+                v[i].y = k + 1 < s1 ? ld_f(src, (int64_t)rr * ld + k + 1) : 0.f;
+                v[i].z = k + 2 < s1 ? ld_f(src, (int64_t)rr * ld + k + 2) : 0.f;
+                v[i].w = k + 3 < s1 ? ld_f(src, (int64_t)rr * ld + k + 3) : 0.f;
+            }
+        } else {
+            if (vec && rr + 3 < R && k < s1) {
+                v[i] = *reinterpret_cast<const float4 *>(src + (int64_t)k * ld + rr);
+            } else if (k < s1) {
+                v[i].x = rr < R ? ld_f(src, (int64_t)k * ld + rr) : 0.f;
+                v[i].y = rr + 1 < R ? ld_f(src, (int64_t)k * ld + rr + 1) : 0.f;
+                v[i].z = rr + 2 < R ? ld_f(src, (int64_t)k * ld + rr + 2) : 0.f;
+                v[i].w = rr + 3 < R ? ld_f(src, (int64_t)k * ld + rr + 3) : 0.f;
+            }
+        }
+    }
+    typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+    for (int i = 0; i < NIT; ++i) {
+        const int it = tid + i * kGT;
+        if (it >= items) continue;
+        const int r = TR ? 4 * (it % 16) : it / per_row, c = TR ? it / 16 : 4 * (it % per_row);
+        if (!TR) {
+            *reinterpret_cast<h4 *>(dst + r * kGS + c) =
+                h4{(_Float16)v[i].x, (_Float16)v[i].y, (_Float16)v[i].z, (_Float16)v[i].w};
+        } else {
+            dst[r * kGS + c] = (_Float16)v[i].x;
+            dst[(r + 1) * kGS + c] = (_Float16)v[i].y;
+            dst[(r + 2) * kGS + c] = (_Float16)v[i].z;
+            dst[(r + 3) * kGS + c] = (_Float16)v[i].w;
+        }
+    }
+}
 
 // C[M x N] = sum_k fp16(A(m, k)) fp16(B(n, k)), FP32 accumulation.
 // A(m, k) = A[m lda + k] (TA false) or A[k lda + m] (TA true); same for B.
 // Split K: block z covers k in [z kc, (z + 1) kc) and writes its slice of the
 // sum to C + z M N (a workspace the split reduction then adds in z order).
-template <typename TAe, typename TBe, bool TA, bool TB>
+// The block stages up to 256 of its k in LDS at once, then runs the MFMAs of
+// those k-steps in order.
+template <typename TAe, typename TBe, bool TA, bool TB, int EPI>
 __global__ __launch_bounds__(kGT) void gemm_kernel(int M, int N, int K, const TAe *A, int lda,
-                                                   const TBe *B, int ldb, float *C, int ldc, int kc) {
+                                                   const TBe *B, int ldb, float *C, int ldc, int kc, EpiArgs ep) {
     __shared__ __attribute__((aligned(16))) _Float16 as[64 * kGS];
     __shared__ __attribute__((aligned(16))) _Float16 bs[64 * kGS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -49,33 +124,27 @@ __global__ __launch_bounds__(kGT) void gemm_kernel(int M, int N, int K, const TA
         for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
     const int kb = blockIdx.z * kc, ke = kb + kc < K ? kb + kc : K;
     C += (int64_t)blockIdx.z * M * N;
-    for (int k0 = kb; k0 < ke; k0 += kGK) {
+    for (int s0 = kb; s0 < ke; s0 += kGKS) {
+        const int s1 = s0 + kGKS < ke ? s0 + kGKS : ke;
+        const int kw = (s1 - s0 + kGK - 1) / kGK * kGK;
         __syncthreads();
-        for (int idx = tid; idx < 64 * kGK; idx += kGT) {
-            const int r = TA ? idx % 64 : idx / kGK, c = TA ? idx / 64 : idx % kGK;
-            const int m = m0 + r, k = k0 + c;
-            float va = 0.f;
-            if (m < M && k < ke) va = TA ? ld_f(A, (int64_t)k * lda + m) : ld_f(A, (int64_t)m * lda + k);
-            as[r * kGS + c] = (_Float16)va;
-        }
-        for (int idx = tid; idx < 64 * kGK; idx += kGT) {
-            const int r = TB ? idx % 64 : idx / kGK, c = TB ? idx / 64 : idx % kGK;
-            const int n = n0 + r, k = k0 + c;
-            float vb = 0.f;
-            if (n < N && k < ke) vb = TB ? ld_f(B, (int64_t)k * ldb + n) : ld_f(B, (int64_t)n * ldb + k);
-            bs[r * kGS + c] = (_Float16)vb;
-        }
+        gemm_stage<TA>(as, A, lda, m0, M, s0, s1, kw, tid);
+        gemm_stage<TB>(bs, B, ldb, n0, N, s0, s1, kw, tid);
         __syncthreads();
-        h8 a[2], b[2];
+        for (int kk = 0; kk < kw; kk += kGK) {
+            h8 a[2], b[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const h8 *>(&as[(wm + 16 * i + r16) * kGS + 8 * q]);
-#pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const h8 *>(&bs[(wn + 16 * j + r16) * kGS + 8 * q]);
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < 2; ++i)
+                a[i] = *reinterpret_cast<const h8 *>(&as[(wm + 16 * i + r16) * kGS + kk + 8 * q]);
 #pragma unroll
             for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[i], b[j], acc[i][j], 0, 0, 0);
+                b[j] = *reinterpret_cast<const h8 *>(&bs[(wn + 16 * j + r16) * kGS + kk + 8 * q]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -84,7 +153,17 @@ __global__ __launch_bounds__(kGT) void gemm_kernel(int M, int N, int K, const TA
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int m = m0 + wm + 16 * i + 4 * q + e, n = n0 + wn + 16 * j + r16;
-                if (m < M && n < N) C[(int64_t)m * ldc + n] = acc[i][j][e];
+                if (m < M && n < N) {
+                    const int64_t o = (int64_t)m * ldc + n;
+                    float v = acc[i][j][e];
+                    if constexpr (EPI == kEpiBiasGelu) {
+                        v += ep.b[n];
+                        ep.H[o] = gelu(v);
+                    } else if constexpr (EPI == kEpiGeluBack) {
+                        v *= gelu_d(ep.Z[o]);
+                    }
+                    C[o] = v;
+                }
             }
 }
 
@@ -99,40 +178,21 @@ __global__ void reduce_slices_kernel(const float *part, int S, int64_t n, float 
 
 // Plain launch (S = 1), or split K over S slices through the workspace ws
 // (S M N floats) and an ordered reduction; C must then be dense (ldc = N).
-template <typename TAe, typename TBe, bool TA, bool TB>
+// An epilogue other than kEpiNone needs S = 1 and dense outputs (ldc = N).
+template <typename TAe, typename TBe, bool TA, bool TB, int EPI = kEpiNone>
 hipError_t gemm(int M, int N, int K, const TAe *A, int lda, const TBe *B, int ldb, float *C, int ldc,
-                hipStream_t s, int S = 1, float *ws = nullptr) {
+                hipStream_t s, int S = 1, float *ws = nullptr, EpiArgs ep = EpiArgs{nullptr, nullptr, nullptr}) {
     const int kc = S > 1 ? ((K + S - 1) / S + kGK - 1) / kGK * kGK : K;
     const int z = S > 1 ? (K + kc - 1) / kc : 1;
+    if (EPI != kEpiNone && (z > 1 || ldc != N)) return hipErrorInvalidValue;
     const dim3 grid((N + 63) / 64, (M + 63) / 64, z);
-    hipLaunchKernelGGL((gemm_kernel<TAe, TBe, TA, TB>), grid, dim3(kGT), 0, s, M, N, K, A, lda, B, ldb,
-                       z > 1 ? ws : C, z > 1 ? N : ldc, kc);
+    hipLaunchKernelGGL((gemm_kernel<TAe, TBe, TA, TB, EPI>), grid, dim3(kGT), 0, s, M, N, K, A, lda, B, ldb,
+                       z > 1 ? ws : C, z > 1 ? N : ldc, kc, ep);
     if (z == 1) return hipGetLastError();
     const int64_t n = (int64_t)M * N;
     hipLaunchKernelGGL(reduce_slices_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0,
                        s, ws, z, n, C);
     return hipGetLastError();
-}
-
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.f + erff(x * 0.70710678118654752f)); }
-__device__ __forceinline__ float gelu_d(float x) {
-    return 0.5f * (1.f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
-}
-
-// Z += b (per column); H = GELU(Z).
-__global__ void bias_gelu_kernel(float *Z, const float *b, float *H, int M, int N) {
-    const int64_t total = (int64_t)M * N;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-        const float z = Z[i] + b[i % N];
-        Z[i] = z;
-        H[i] = gelu(z);
-    }
-}
-
-// dZ = dH * GELU'(Z), in place in dH.
-__global__ void gelu_back_kernel(float *dH, const float *Z, int64_t total) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
-        dH[i] *= gelu_d(Z[i]);
 }
 
 // Head and loss: y_b = sum_j fp16(H_bj) fp16(w_j) + c.  Training: dy_b = 2 (y_b - t_b)
@@ -411,11 +471,13 @@ hipError_t mlp_pass(const MlpBuffers &m, int B, const float *Xb, const float *tb
     float *gW1 = m.G, *gb1 = gW1 + (int64_t)H * in, *gW2 = gb1 + H, *gb2 = gW2 + (int64_t)H * H, *gw3 = gb2 + H,
           *gb3 = gw3 + H;
     hipError_t e;
-    const int eb = (int)std::min<int64_t>(((int64_t)B * H + 255) / 256, 8192);
-    if ((e = gemm<float, float, false, false>(B, H, in, Xb, in, W1, in, m.Z1, H, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(bias_gelu_kernel, dim3(eb), dim3(256), 0, s, m.Z1, b1, m.H1, B, H);
-    if ((e = gemm<float, float, false, false>(B, H, H, m.H1, H, W2, H, m.Z2, H, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(bias_gelu_kernel, dim3(eb), dim3(256), 0, s, m.Z2, b2, m.H2, B, H);
+    // Z = X W^T + b and H = GELU(Z), per layer (bias and activation in the GEMM epilogue)
+    if ((e = gemm<float, float, false, false, kEpiBiasGelu>(B, H, in, Xb, in, W1, in, m.Z1, H, s, 1, nullptr,
+                                                            EpiArgs{b1, m.H1, nullptr})) != hipSuccess)
+        return e;
+    if ((e = gemm<float, float, false, false, kEpiBiasGelu>(B, H, H, m.H1, H, W2, H, m.Z2, H, s, 1, nullptr,
+                                                            EpiArgs{b2, m.H2, nullptr})) != hipSuccess)
+        return e;
     hipLaunchKernelGGL(head_kernel, dim3(B), dim3(256), 0, s, m.H2, m.Z2, w3, b3, tb, y, m.dy, m.dZ2, m.lrow, H,
                        train ? 1 : 0);
     if (!train) return hipGetLastError();
@@ -426,8 +488,9 @@ hipError_t mlp_pass(const MlpBuffers &m, int B, const float *Xb, const float *tb
     if ((e = gemm<float, float, true, true>(H, H, B, m.dZ2, H, m.H1, H, gW2, H, s, ksplit(B), m.ws)) != hipSuccess)
         return e;
     if ((e = colsum<false>(m.dZ2, nullptr, B, H, gb2, m.ws, s)) != hipSuccess) return e;
-    if ((e = gemm<float, float, false, true>(B, H, H, m.dZ2, H, W2, H, m.dZ1, H, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(gelu_back_kernel, dim3(eb), dim3(256), 0, s, m.dZ1, m.Z1, (int64_t)B * H);
+    if ((e = gemm<float, float, false, true, kEpiGeluBack>(B, H, H, m.dZ2, H, W2, H, m.dZ1, H, s, 1, nullptr,
+                                                           EpiArgs{nullptr, nullptr, m.Z1})) != hipSuccess)
+        return e;
     // layer 1: dW1 = dZ1^T X, db1 = column sums of dZ1
     if ((e = gemm<float, float, true, true>(H, in, B, m.dZ1, H, Xb, in, gW1, in, s, ksplit(B), m.ws)) != hipSuccess)
         return e;
