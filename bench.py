@@ -31,7 +31,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "NLL+grad event-evals/s, batched vs single-V at 1e-6 rel err; %HBM / %MFMA peak"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_nll_stream_k16.json")
+# committed counter summaries of the single-V kernel, one per launch configuration
+TRAFFIC_GLOB = os.path.join(ROOT, "profiles", "traffic_nll_stream_k16*.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1108_5882_amd", "csrc", "nll_stream_impl.hpp")
 
 
@@ -45,18 +46,20 @@ def kernel_hash() -> str:
 
 
 def stored_traffic(units_per_launch, kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
-    when the kernel source or the launch configuration differs from the one
-    the counters were taken on."""
-    try:
-        with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
-        return None
-    if (t.get("kernel_sha256_16") != kernel_hash() or t.get("units_per_launch") != units_per_launch
-            or t.get("kernel") != kernel):
-        return None
-    return t.get("hbm_bytes_per_launch")
+    """HBM bytes per launch from the committed rocprofv3 counter summary taken on
+    this kernel source, launch configuration and rows per launch, or None when
+    there is none."""
+    import glob
+    for path in sorted(glob.glob(TRAFFIC_GLOB)):
+        try:
+            with open(path) as f:
+                t = json.load(f)
+        except (OSError, ValueError):
+            continue
+        if (t.get("kernel_sha256_16") == kernel_hash() and t.get("units_per_launch") == units_per_launch
+                and t.get("kernel") == kernel):
+            return t.get("hbm_bytes_per_launch")
+    return None
 
 
 def host_threads() -> int:
