@@ -32,7 +32,8 @@ def _scale(Ad, V, h_mc):
 
 CASES = [(16, 5003, 20011, "f32"), (4, 3000, 9000, "f32"), (33, 2049, 6007, "f32"), (1, 1000, 3000, "f32"),
          (48, 1500, 4000, "f32"), (64, 1201, 3000, "f32"), (16, 3001, 9007, "f64"), (5, 2000, 6000, "f64"),
-         (64, 800, 2000, "f64"), (16, 200003, 30011, "f32"), (48, 60001, 20011, "f32")]
+         (64, 800, 2000, "f64"), (16, 200003, 30011, "f32"), (48, 60001, 20011, "f32"), (56, 1001, 3001, "f32"),
+         (9, 2003, 5003, "f32")]
 
 
 @pytest.mark.parametrize("k,nd,nm,prec", CASES)
