@@ -271,6 +271,9 @@ struct MlpBuffers {
     float *Xb, *tb;                   // gathered mini-batch features and targets
     float *ws;                        // reduction workspace, mlp_workspace_floats(in, hidden) floats
     int *step, *batch, *bad;          // Adam step count, mini-batch index, bad-index flag (device)
+    // fused path (hidden width 256): per-slice gradient sums and losses, Z scratch, arrival counter
+    float *fpart = nullptr, *floss = nullptr, *fzs = nullptr;
+    unsigned *farrive = nullptr;
 };
 
 int64_t mlp_param_count(int in, int hidden);
@@ -286,6 +289,17 @@ hipError_t mlp_targets(const double *nll, int64_t n, float *t, hipStream_t s);
 hipError_t mlp_pass(const MlpBuffers &m, int B, const float *Xb, const float *tb, float *y, bool train, float *hist,
                     hipStream_t s);
 hipError_t mlp_scale(const float *x, int64_t n, float scale, float *out, hipStream_t s);
+// Fused training pass (mlp_fused.hip), hidden width 256 and in <= 128 only: per
+// slice of 32 rows (X rows perm[*m.batch B + r] when perm is set, else rows
+// 0 .. B-1) the forward pass, loss and gradient sums, then the slices added in
+// order into m.G and m.loss (hist[*m.batch] too when set); with adam, Adam on
+// m.P with m.G * gscale at step *m.step + 1 instead of writing m.G, and
+// *m.step, *m.batch advanced.
+bool mlp_fused_ok(const MlpBuffers &m);
+int mlp_fused_slices(int B);
+size_t mlp_fused_zs_floats(int max_batch);
+hipError_t mlp_fused_pass(const MlpBuffers &m, int B, const float *X, const float *t, const int *perm, int64_t n,
+                          bool adam, float gscale, float lr, float *hist, hipStream_t s);
 // Adam on m.P with gradient m.G * gscale; step count at m.step (not advanced here).
 hipError_t mlp_adam(const MlpBuffers &m, float gscale, float lr, hipStream_t s);
 // Rows perm[*m.batch * B + r] of X [n][in] and t into m.Xb, m.tb (*m.bad set

@@ -144,6 +144,16 @@ pwa_status pwa_mlp_create(pwa_mlp **out, int device, int32_t in, int32_t hidden,
     b.step = ints;
     b.batch = ints + 1;
     b.bad = ints + 2;
+    b.farrive = reinterpret_cast<unsigned *>(ints + 3);
+    if (hidden == 256 && in <= 128) {   // buffers of the fused training pass
+        const size_t S = (size_t)mlp_fused_slices(max_batch);
+        if ((st = alloc(m, &b.fpart, S * (size_t)b.nparams)) || (st = alloc(m, &b.floss, S)) ||
+            (st = alloc(m, &b.fzs, mlp_fused_zs_floats(max_batch)))) {
+            g_lerr = m->err;
+            pwa_mlp_destroy(m);
+            return st;
+        }
+    }
     hipError_t e = hipMemsetAsync(b.P, 0, sizeof(float) * b.nparams, m->stream);
     if (e == hipSuccess) e = hipMemsetAsync(b.M1, 0, sizeof(float) * b.nparams, m->stream);
     if (e == hipSuccess) e = hipMemsetAsync(b.M2, 0, sizeof(float) * b.nparams, m->stream);
@@ -231,7 +241,13 @@ pwa_status pwa_mlp_loss_grad(pwa_mlp *m, const float *X, const float *t, int32_t
     if (B < 1 || B > m->m.max_batch) return lfail(m, PWA_E_INVAL, "batch %d outside 1..%d", B, m->m.max_batch);
     Guard g(m->device);
     const MlpBuffers &b = m->m;
-    L_HIP(m, mlp_pass(b, B, X, t, b.y, true, nullptr, m->stream), "training pass launch");
+    if (mlp_fused_ok(b)) {
+        L_HIP(m, mlp_set_int(b.bad, 0, m->stream), "reset launch");
+        L_HIP(m, mlp_fused_pass(b, B, X, t, nullptr, B, false, 1.0f, 0.0f, nullptr, m->stream),
+              "fused training pass launch");
+    } else {
+        L_HIP(m, mlp_pass(b, B, X, t, b.y, true, nullptr, m->stream), "training pass launch");
+    }
     L_HIP(m, mlp_scale(b.G, b.nparams, 1.0f / (float)B, G, m->stream), "scale launch");
     float l = 0.f;
     L_HIP(m, hipMemcpyAsync(&l, b.loss, sizeof(float), hipMemcpyDeviceToHost, m->stream), "hipMemcpyAsync(loss)");
@@ -252,10 +268,15 @@ pwa_status pwa_mlp_train(pwa_mlp *m, const float *X, const float *t, int64_t n, 
     if (!m->exec || !(m->key == key)) {
         drop_graph(m);
         L_HIP(m, hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-        hipError_t ec = mlp_gather(b, X, t, n, perm, batch, m->stream);
-        if (ec == hipSuccess) ec = mlp_pass(b, batch, b.Xb, b.tb, b.y, true, loss_hist, m->stream);
-        if (ec == hipSuccess) ec = mlp_adam(b, 1.0f / (float)batch, lr, m->stream);
-        if (ec == hipSuccess) ec = mlp_step_inc(b, m->stream);
+        hipError_t ec;
+        if (mlp_fused_ok(b)) {   // two launches: slices, then their ordered sum with Adam
+            ec = mlp_fused_pass(b, batch, X, t, perm, n, true, 1.0f / (float)batch, lr, loss_hist, m->stream);
+        } else {
+            ec = mlp_gather(b, X, t, n, perm, batch, m->stream);
+            if (ec == hipSuccess) ec = mlp_pass(b, batch, b.Xb, b.tb, b.y, true, loss_hist, m->stream);
+            if (ec == hipSuccess) ec = mlp_adam(b, 1.0f / (float)batch, lr, m->stream);
+            if (ec == hipSuccess) ec = mlp_step_inc(b, m->stream);
+        }
         hipError_t e = hipStreamEndCapture(m->stream, &m->graph);
         if (ec != hipSuccess) e = ec;
         if (e == hipSuccess) e = hipGraphInstantiate(&m->exec, m->graph, nullptr, nullptr, 0);

@@ -1,0 +1,366 @@
+// Fused training pass of the surrogate network at hidden width 256: one
+// launch computes, per slice of 32 mini-batch rows, the forward pass, the
+// loss and every parameter gradient of the slice; a second launch adds the
+// slices in order and applies Adam (or returns the summed gradient).  The
+// arithmetic is that of the layer-by-layer kernels in mlp.hip: every matrix
+// product rounds both operands to FP16 and accumulates in FP32
+// (v_mfma_f32_16x16x32_f16), biases and activations are FP32, the head and
+// the weight-3 gradient use the FP16-rounded activations.  Only the order in
+// which the rows of a mini-batch are added differs (slices of 32 rows, added
+// in slice order).
+#include "internal.hpp"
+
+namespace pwa {
+namespace {
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kFR = 32;                 // rows per slice (one workgroup)
+constexpr int kFH = 256;                // hidden width of the fused path
+constexpr int kFT = 256;                // threads per workgroup
+constexpr int kSH = kFH + 8;            // row stride (halfs) of [32][256] planes
+constexpr int kST = kFR + 8;            // row stride (halfs) of transposed [256][32] planes
+
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_d(float x) {
+    return 0.5f * (1.f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+}
+
+struct FusedArgs {
+    const float *P;                     // parameters W1 [H][in], b1, W2 [H][H], b2, w3, b3
+    const float *X, *t;                 // features [n][in] and targets [n]
+    const int *perm;                    // null: rows 0 .. B-1 of X; else rows perm[*batch B + r]
+    const int *batch;                   // mini-batch index (with perm)
+    int64_t n;
+    int B, in;
+    int64_t nparams;
+    float *part;                        // [slice][nparams] gradient sums of the slice's rows
+    float *lossp;                       // [slice] sum of the squared errors
+    float *zs;                          // [slice][2][32][256] Z1 then Z2 (FP32)
+    int *bad;
+};
+
+// C[32 x 64] += A[32 x K] B[64 x K]^T, A and B FP16 in LDS with k contiguous
+// (row strides sa, sb); wave w owns row tile w & 1 and column tiles
+// 2 (w >> 1), 2 (w >> 1) + 1; item e of acc[j] is row 16 (w & 1) + 4 q + e,
+// column 16 (2 (w >> 1) + j) + r16 of the chunk.
+__device__ __forceinline__ void chunk_mfma(const _Float16 *A, int sa, const _Float16 *B, int sb, int K, f4 acc[2],
+                                           int wave, int q, int r16) {
+    const int rt = wave & 1, ct = 2 * (wave >> 1);
+    for (int kk = 0; kk < K; kk += 32) {
+        const h8 a = *reinterpret_cast<const h8 *>(A + (16 * rt + r16) * sa + kk + 8 * q);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const h8 b = *reinterpret_cast<const h8 *>(B + (16 * (ct + j) + r16) * sb + kk + 8 * q);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc[j], 0, 0, 0);
+        }
+    }
+}
+
+// dst[r][c] = fp16(src[(r0 + r) ld + c]) for 64 rows and c < kw (zero at c >= cols),
+// row stride sd halfs; four columns per item (16-byte loads when aligned).
+__device__ __forceinline__ void stage_rows(_Float16 *dst, int sd, const float *src, int ld, int r0, int cols, int kw,
+                                           int tid) {
+    const int per = kw / 4;
+    const bool vec = ld % 4 == 0 && cols % 4 == 0 && (reinterpret_cast<uintptr_t>(src) & 15) == 0;
+    for (int it = tid; it < 64 * per; it += kFT) {
+        const int r = it / per, c = 4 * (it % per);
+        const float *p = src + (int64_t)(r0 + r) * ld + c;
+        float4 v = float4{0.f, 0.f, 0.f, 0.f};
+        if (vec && c + 3 < cols) {
+            v = *reinterpret_cast<const float4 *>(p);
+        } else {
+            v.x = c < cols ? p[0] : 0.f;
+            v.y = c + 1 < cols ? p[1] : 0.f;
+            v.z = c + 2 < cols ? p[2] : 0.f;
+            v.w = c + 3 < cols ? p[3] : 0.f;
+        }
+        *reinterpret_cast<h4 *>(dst + r * sd + c) = h4{(_Float16)v.x, (_Float16)v.y, (_Float16)v.z, (_Float16)v.w};
+    }
+}
+
+// dst[c][k] = fp16(src[k ld + c0 + c]) for 64 columns c and k < 256 (the transpose
+// of a 256 x 64 block of a row-major matrix), row stride sd halfs.
+__device__ __forceinline__ void stage_cols(_Float16 *dst, int sd, const float *src, int ld, int c0, int tid) {
+    for (int it = tid; it < 16 * kFH; it += kFT) {
+        const int k = it / 16, c = 4 * (it % 16);
+        const float4 v = *reinterpret_cast<const float4 *>(src + (int64_t)k * ld + c0 + c);
+        dst[c * sd + k] = (_Float16)v.x;
+        dst[(c + 1) * sd + k] = (_Float16)v.y;
+        dst[(c + 2) * sd + k] = (_Float16)v.z;
+        dst[(c + 3) * sd + k] = (_Float16)v.w;
+    }
+}
+
+template <int INP>
+struct FusedSmem {
+    static constexpr int SX = INP + 8;
+    _Float16 xr[kFR * SX];              // X, rows
+    _Float16 xt[INP * kST];             // X, transposed
+    _Float16 h1r[kFR * kSH];            // fp16(H1), rows
+    _Float16 h1t[kFH * kST];            // fp16(H1), transposed
+    _Float16 d2r[kFR * kSH];            // fp16(dZ2), rows
+    _Float16 d2t[kFH * kST];            // fp16(dZ2), transposed
+    _Float16 hx[kFH * kST];             // fp16(H2) rows (first kFR * kSH), later fp16(dZ1) transposed
+    _Float16 w[64 * (kFH + 8 > INP + 8 ? kFH + 8 : INP + 8)];   // one staged 64-row weight chunk
+    float tgt[kFR], dy[kFR], lrow[kFR];
+    int src[kFR];
+};
+
+// One workgroup per slice of 32 rows.
+template <int INP>
+__global__ __launch_bounds__(kFT) void mlp_fused_kernel(FusedArgs a) {
+    static_assert(kFR * kSH <= kFH * kST, "H2 rows must fit in the dZ1 plane");
+    __shared__ __attribute__((aligned(16))) FusedSmem<INP> sm;
+    constexpr int SX = FusedSmem<INP>::SX;
+    constexpr int SW = kFH + 8;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, q = lane >> 4, r16 = lane & 15;
+    const int slice = blockIdx.x, in = a.in;
+    const float *W1 = a.P, *b1 = W1 + (int64_t)kFH * in, *W2 = b1 + kFH, *b2 = W2 + (int64_t)kFH * kFH,
+                *w3 = b2 + kFH, *b3 = w3 + kFH;
+    float *G = a.part + (int64_t)slice * a.nparams;
+    float *gW1 = G, *gb1 = gW1 + (int64_t)kFH * in, *gW2 = gb1 + kFH, *gb2 = gW2 + (int64_t)kFH * kFH,
+          *gw3 = gb2 + kFH, *gb3 = gw3 + kFH;
+    float *Z1 = a.zs + (int64_t)slice * 2 * kFR * kFH, *Z2 = Z1 + kFR * kFH;
+    const int rows = a.B - slice * kFR < kFR ? a.B - slice * kFR : kFR;
+
+    // rows of the slice (a bad permutation entry reads row 0 and raises the flag)
+    if (tid < kFR) {
+        int64_t s = -1;
+        if (tid < rows) {
+            const int64_t gr = (int64_t)slice * kFR + tid;
+            s = a.perm ? (int64_t)a.perm[(int64_t)(*a.batch) * a.B + gr] : gr;
+            if (s < 0 || s >= a.n) {
+                atomicOr(a.bad, 1);
+                s = 0;
+            }
+        }
+        sm.src[tid] = (int)s;
+        sm.tgt[tid] = s >= 0 ? a.t[s] : 0.f;
+    }
+    __syncthreads();
+    // X rows and their transpose (zero past the slice's rows and past in)
+    for (int it = tid; it < kFR * INP; it += kFT) {
+        const int r = it / INP, c = it % INP;
+        const int s = sm.src[r];
+        const _Float16 v = (_Float16)((s >= 0 && c < in) ? a.X[(int64_t)s * in + c] : 0.f);
+        sm.xr[r * SX + c] = v;
+        sm.xt[c * kST + r] = v;
+    }
+
+    // layer 1: Z1 = X W1^T + b1, H1 = GELU(Z1), 64 features per chunk
+    for (int f0 = 0; f0 < kFH; f0 += 64) {
+        __syncthreads();
+        stage_rows(sm.w, SX, W1, in, f0, in, INP, tid);
+        __syncthreads();
+        f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+        chunk_mfma(sm.xr, SX, sm.w, SX, INP, acc, wave, q, r16);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = 16 * (wave & 1) + 4 * q + e, f = f0 + 16 * (2 * (wave >> 1) + j) + r16;
+                const float z = acc[j][e] + b1[f];
+                const _Float16 h = (_Float16)gelu(z);
+                Z1[r * kFH + f] = z;
+                sm.h1r[r * kSH + f] = h;
+                sm.h1t[f * kST + r] = h;
+            }
+    }
+    // layer 2: Z2 = H1 W2^T + b2, fp16(H2) rows into hx
+    _Float16 *h2r = sm.hx;
+    for (int f0 = 0; f0 < kFH; f0 += 64) {
+        __syncthreads();
+        stage_rows(sm.w, SW, W2, kFH, f0, kFH, kFH, tid);
+        __syncthreads();
+        f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+        chunk_mfma(sm.h1r, kSH, sm.w, SW, kFH, acc, wave, q, r16);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = 16 * (wave & 1) + 4 * q + e, f = f0 + 16 * (2 * (wave >> 1) + j) + r16;
+                const float z = acc[j][e] + b2[f];
+                Z2[r * kFH + f] = z;
+                h2r[r * kSH + f] = (_Float16)gelu(z);
+            }
+    }
+    __syncthreads();
+    // head: y = fp16(H2) . fp16(w3) + b3 (8 lanes per row, lane-order sums), dy, loss
+    {
+        const int r = tid >> 3, l8 = tid & 7;
+        float s = 0.f;
+        for (int j = l8; j < kFH; j += 8) s += (float)h2r[r * kSH + j] * (float)(_Float16)w3[j];
+        s += __shfl_xor(s, 1);
+        s += __shfl_xor(s, 2);
+        s += __shfl_xor(s, 4);
+        if (l8 == 0) {
+            const float yb = s + b3[0];
+            const bool ok = r < rows;
+            sm.dy[r] = ok ? 2.f * (yb - sm.tgt[r]) : 0.f;
+            sm.lrow[r] = ok ? (yb - sm.tgt[r]) * (yb - sm.tgt[r]) : 0.f;
+        }
+    }
+    __syncthreads();
+    // dZ2 = dy fp16(w3) GELU'(Z2) (rows and transpose); per feature j: db2, dw3; db3 and the loss
+    {
+        const int j = tid;
+        const float wj = (float)(_Float16)w3[j];
+        float z2[kFR];                                  // the column's Z2, all loads in flight
+#pragma unroll
+        for (int r = 0; r < kFR; ++r) z2[r] = Z2[r * kFH + j];
+        float sb = 0.f, sw = 0.f;
+#pragma unroll
+        for (int r = 0; r < kFR; ++r) {
+            const float d = sm.dy[r] * wj * gelu_d(z2[r]);
+            const _Float16 dh = (_Float16)d;
+            sm.d2r[r * kSH + j] = dh;
+            sm.d2t[j * kST + r] = dh;
+            sb += d;
+            sw += sm.dy[r] * (float)h2r[r * kSH + j];
+        }
+        gb2[j] = sb;
+        gw3[j] = sw;
+        if (j == 0) {
+            float sd = 0.f, sl = 0.f;
+            for (int r = 0; r < kFR; ++r) {
+                sd += sm.dy[r];
+                sl += sm.lrow[r];
+            }
+            gb3[0] = sd;
+            a.lossp[slice] = sl;
+        }
+    }
+    __syncthreads();
+    // dW2[i][j] = sum_r fp16(dZ2[r][i]) fp16(H1[r][j]): 256 tiles of 16 x 16, one MFMA each
+    for (int tl = wave; tl < (kFH / 16) * (kFH / 16); tl += 4) {
+        const int ti = tl / (kFH / 16), tj = tl % (kFH / 16);
+        const h8 av = *reinterpret_cast<const h8 *>(sm.d2t + (16 * ti + r16) * kST + 8 * q);
+        const h8 bv = *reinterpret_cast<const h8 *>(sm.h1t + (16 * tj + r16) * kST + 8 * q);
+        const f4 d = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bv, f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) gW2[(int64_t)(16 * ti + 4 * q + e) * kFH + 16 * tj + r16] = d[e];
+    }
+    // dH1 = dZ2 W2 (W2 staged transposed, 64 input features per chunk), dZ1 = dH1 GELU'(Z1)
+    _Float16 *d1t = sm.hx;                              // H2 rows are no longer read
+    for (int c0 = 0; c0 < kFH; c0 += 64) {
+        __syncthreads();
+        stage_cols(sm.w, SW, W2, kFH, c0, tid);
+        __syncthreads();
+        f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+        chunk_mfma(sm.d2r, kSH, sm.w, SW, kFH, acc, wave, q, r16);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = 16 * (wave & 1) + 4 * q + e, i = c0 + 16 * (2 * (wave >> 1) + j) + r16;
+                const float d = acc[j][e] * gelu_d(Z1[r * kFH + i]);
+                Z1[r * kFH + i] = d;                    // dZ1 in place of Z1 (the same thread read it)
+                d1t[i * kST + r] = (_Float16)d;
+            }
+    }
+    __syncthreads();
+    // db1[i] = sum_r dZ1[r][i]
+    {
+        const int i = tid;
+        float d1[kFR];
+#pragma unroll
+        for (int r = 0; r < kFR; ++r) d1[r] = Z1[r * kFH + i];
+        float s = 0.f;
+#pragma unroll
+        for (int r = 0; r < kFR; ++r) s += d1[r];
+        gb1[i] = s;
+    }
+    // dW1[i][c] = sum_r fp16(dZ1[r][i]) fp16(X[r][c])
+    for (int tl = wave; tl < (kFH / 16) * (INP / 16); tl += 4) {
+        const int ti = tl / (INP / 16), tc = tl % (INP / 16);
+        const h8 av = *reinterpret_cast<const h8 *>(d1t + (16 * ti + r16) * kST + 8 * q);
+        const h8 bv = *reinterpret_cast<const h8 *>(sm.xt + (16 * tc + r16) * kST + 8 * q);
+        const f4 d = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bv, f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        const int c = 16 * tc + r16;
+        if (c < in) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) gW1[(int64_t)(16 * ti + 4 * q + e) * in + c] = d[e];
+        }
+    }
+}
+
+// Slice sums in slice order: G = sum_s part[s] (loss: sum_s lossp[s] / B, also
+// hist[*batch]).  With Adam the sum times gscale updates P, M1, M2 at step
+// *step + 1, and the last workgroup to finish advances *step and *batch.
+__global__ __launch_bounds__(256) void mlp_fused_reduce_kernel(const float *part, const float *lossp, int S,
+                                                               int64_t np, int B, float *G, float *loss, float *hist,
+                                                               int adam, float *P, float *M1, float *M2, float gscale,
+                                                               float lr, int *step, int *batch, unsigned *arrive) {
+    __shared__ unsigned s_last;
+    const int t = adam ? *step + 1 : 0;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = adam ? 1.f - powf(b1, (float)t) : 1.f, c2 = adam ? 1.f - powf(b2, (float)t) : 1.f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
+        float g = 0.f;
+        for (int s = 0; s < S; ++s) g += part[(int64_t)s * np + i];
+        if (!adam) {
+            G[i] = g;
+        } else {
+            const float gi = g * gscale;
+            const float mi = b1 * M1[i] + (1.f - b1) * gi;
+            const float vi = b2 * M2[i] + (1.f - b2) * gi * gi;
+            M1[i] = mi;
+            M2[i] = vi;
+            P[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        float l = 0.f;
+        for (int s = 0; s < S; ++s) l += lossp[s];
+        *loss = l / (float)B;
+        if (hist) hist[*batch] = l / (float)B;
+    }
+    if (!adam) return;
+    // every workgroup has used *step (and block 0 *batch) before it arrives: the
+    // last one to arrive advances them
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(arrive, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (s_last && threadIdx.x == 0) {
+        *step += 1;
+        *batch += 1;
+        *arrive = 0u;
+    }
+}
+
+template <int INP>
+hipError_t launch_fused(const FusedArgs &a, int S, hipStream_t s) {
+    hipLaunchKernelGGL(mlp_fused_kernel<INP>, dim3(S), dim3(kFT), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool mlp_fused_ok(const MlpBuffers &m) { return m.hidden == kFH && m.in >= 1 && m.in <= 128 && m.fpart; }
+
+int mlp_fused_slices(int B) { return (B + kFR - 1) / kFR; }
+
+size_t mlp_fused_zs_floats(int max_batch) { return (size_t)mlp_fused_slices(max_batch) * 2 * kFR * kFH; }
+
+hipError_t mlp_fused_pass(const MlpBuffers &m, int B, const float *X, const float *t, const int *perm, int64_t n,
+                          bool adam, float gscale, float lr, float *hist, hipStream_t s) {
+    if (!mlp_fused_ok(m) || B < 1 || B > m.max_batch) return hipErrorInvalidValue;
+    const int S = mlp_fused_slices(B);
+    FusedArgs a{m.P, X, t, perm, m.batch, n, B, m.in, m.nparams, m.fpart, m.floss, m.fzs, m.bad};
+    hipError_t e;
+    const int inp = (m.in + 31) / 32 * 32;
+    e = inp == 32 ? launch_fused<32>(a, S, s)
+        : inp == 64 ? launch_fused<64>(a, S, s)
+        : inp == 96 ? launch_fused<96>(a, S, s)
+                    : launch_fused<128>(a, S, s);
+    if (e != hipSuccess) return e;
+    const int blocks = (int)std::min<int64_t>((m.nparams + 255) / 256, 1024);
+    hipLaunchKernelGGL(mlp_fused_reduce_kernel, dim3(blocks), dim3(256), 0, s, m.fpart, m.floss, S, m.nparams, B, m.G,
+                       m.loss, hist, adam ? 1 : 0, m.P, m.M1, m.M2, gscale, lr, m.step, m.batch, m.farrive);
+    return hipGetLastError();
+}
+
+}  // namespace pwa
