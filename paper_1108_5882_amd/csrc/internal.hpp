@@ -273,6 +273,7 @@ struct MlpBuffers {
     int *step, *batch, *bad;          // Adam step count, mini-batch index, bad-index flag (device)
     // fused path (hidden width 256): per-slice gradient sums and losses, Z scratch, arrival counter
     float *fpart = nullptr, *floss = nullptr, *fzs = nullptr;
+    _Float16 *fwh = nullptr;          // fp16 W1 [256][128], W2 [256][256], W2^T [256][256]
     unsigned *farrive = nullptr;
 };
 
@@ -298,6 +299,10 @@ hipError_t mlp_scale(const float *x, int64_t n, float scale, float *out, hipStre
 bool mlp_fused_ok(const MlpBuffers &m);
 int mlp_fused_slices(int B);
 size_t mlp_fused_zs_floats(int max_batch);
+size_t mlp_fused_wh_halfs();
+// fp16 copies of the current weights for the fused pass (after any change of m.P
+// other than the fused pass's own Adam steps)
+hipError_t mlp_fused_weights(const MlpBuffers &m, hipStream_t s);
 hipError_t mlp_fused_pass(const MlpBuffers &m, int B, const float *X, const float *t, const int *perm, int64_t n,
                           bool adam, float gscale, float lr, float *hist, hipStream_t s);
 // Adam on m.P with gradient m.G * gscale; step count at m.step (not advanced here).

@@ -148,7 +148,8 @@ pwa_status pwa_mlp_create(pwa_mlp **out, int device, int32_t in, int32_t hidden,
     if (hidden == 256 && in <= 128) {   // buffers of the fused training pass
         const size_t S = (size_t)mlp_fused_slices(max_batch);
         if ((st = alloc(m, &b.fpart, S * (size_t)b.nparams)) || (st = alloc(m, &b.floss, S)) ||
-            (st = alloc(m, &b.fzs, mlp_fused_zs_floats(max_batch)))) {
+            (st = alloc(m, &b.fzs, mlp_fused_zs_floats(max_batch))) ||
+            (st = alloc(m, &b.fwh, mlp_fused_wh_halfs()))) {
             g_lerr = m->err;
             pwa_mlp_destroy(m);
             return st;
@@ -243,6 +244,7 @@ pwa_status pwa_mlp_loss_grad(pwa_mlp *m, const float *X, const float *t, int32_t
     const MlpBuffers &b = m->m;
     if (mlp_fused_ok(b)) {
         L_HIP(m, mlp_set_int(b.bad, 0, m->stream), "reset launch");
+        L_HIP(m, mlp_fused_weights(b, m->stream), "weights launch");
         L_HIP(m, mlp_fused_pass(b, B, X, t, nullptr, B, false, 1.0f, 0.0f, nullptr, m->stream),
               "fused training pass launch");
     } else {
@@ -288,6 +290,7 @@ pwa_status pwa_mlp_train(pwa_mlp *m, const float *X, const float *t, int64_t n, 
     }
     L_HIP(m, mlp_set_int(b.batch, 0, m->stream), "reset launch");
     L_HIP(m, mlp_set_int(b.bad, 0, m->stream), "reset launch");
+    if (mlp_fused_ok(b)) L_HIP(m, mlp_fused_weights(b, m->stream), "weights launch");
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (avg_ms) {
         L_HIP(m, hipEventCreate(&e0), "hipEventCreate");

@@ -39,6 +39,9 @@ struct FusedArgs {
     float *part;                        // [slice][nparams] gradient sums of the slice's rows
     float *lossp;                       // [slice] sum of the squared errors
     float *zs;                          // [slice][2][32][256] Z1 then Z2 (FP32)
+    const _Float16 *w1h;                // fp16(W1) [256][INP] (zero past in)
+    const _Float16 *w2h;                // fp16(W2) [256][256]
+    const _Float16 *w2th;               // fp16(W2) transposed [256][256]
     int *bad;
 };
 
@@ -59,40 +62,27 @@ __device__ __forceinline__ void chunk_mfma(const _Float16 *A, int sa, const _Flo
     }
 }
 
-// dst[r][c] = fp16(src[(r0 + r) ld + c]) for 64 rows and c < kw (zero at c >= cols),
-// row stride sd halfs; four columns per item (16-byte loads when aligned).
-__device__ __forceinline__ void stage_rows(_Float16 *dst, int sd, const float *src, int ld, int r0, int cols, int kw,
-                                           int tid) {
-    const int per = kw / 4;
-    const bool vec = ld % 4 == 0 && cols % 4 == 0 && (reinterpret_cast<uintptr_t>(src) & 15) == 0;
-    for (int it = tid; it < 64 * per; it += kFT) {
-        const int r = it / per, c = 4 * (it % per);
-        const float *p = src + (int64_t)(r0 + r) * ld + c;
-        float4 v = float4{0.f, 0.f, 0.f, 0.f};
-        if (vec && c + 3 < cols) {
-            v = *reinterpret_cast<const float4 *>(p);
-        } else {
-            v.x = c < cols ? p[0] : 0.f;
-            v.y = c + 1 < cols ? p[1] : 0.f;
-            v.z = c + 2 < cols ? p[2] : 0.f;
-            v.w = c + 3 < cols ? p[3] : 0.f;
+// A chunk of 64 rows of an FP16 matrix with row length W (halfs) moves from
+// global memory through registers (issued early) into LDS rows of stride sd.
+template <int W>
+struct Chunk {
+    static constexpr int N = 64 * W / 8 / kFT;          // 16-byte pieces per thread
+    uint4 v[N];
+    __device__ __forceinline__ void load(const _Float16 *src, int r0, int tid) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const int it = tid + i * kFT, r = it / (W / 8), c = 8 * (it % (W / 8));
+            v[i] = *reinterpret_cast<const uint4 *>(src + (int64_t)(r0 + r) * W + c);
         }
-        *reinterpret_cast<h4 *>(dst + r * sd + c) = h4{(_Float16)v.x, (_Float16)v.y, (_Float16)v.z, (_Float16)v.w};
     }
-}
-
-// dst[c][k] = fp16(src[k ld + c0 + c]) for 64 columns c and k < 256 (the transpose
-// of a 256 x 64 block of a row-major matrix), row stride sd halfs.
-__device__ __forceinline__ void stage_cols(_Float16 *dst, int sd, const float *src, int ld, int c0, int tid) {
-    for (int it = tid; it < 16 * kFH; it += kFT) {
-        const int k = it / 16, c = 4 * (it % 16);
-        const float4 v = *reinterpret_cast<const float4 *>(src + (int64_t)k * ld + c0 + c);
-        dst[c * sd + k] = (_Float16)v.x;
-        dst[(c + 1) * sd + k] = (_Float16)v.y;
-        dst[(c + 2) * sd + k] = (_Float16)v.z;
-        dst[(c + 3) * sd + k] = (_Float16)v.w;
+    __device__ __forceinline__ void store(_Float16 *dst, int sd, int tid) const {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const int it = tid + i * kFT, r = it / (W / 8), c = 8 * (it % (W / 8));
+            *reinterpret_cast<uint4 *>(dst + r * sd + c) = v[i];
+        }
     }
-}
+};
 
 template <int INP>
 struct FusedSmem {
@@ -150,42 +140,53 @@ __global__ __launch_bounds__(kFT) void mlp_fused_kernel(FusedArgs a) {
         sm.xt[c * kST + r] = v;
     }
 
-    // layer 1: Z1 = X W1^T + b1, H1 = GELU(Z1), 64 features per chunk
-    for (int f0 = 0; f0 < kFH; f0 += 64) {
-        __syncthreads();
-        stage_rows(sm.w, SX, W1, in, f0, in, INP, tid);
-        __syncthreads();
-        f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
-        chunk_mfma(sm.xr, SX, sm.w, SX, INP, acc, wave, q, r16);
+    // layer 1: Z1 = X W1^T + b1, H1 = GELU(Z1), 64 features per chunk (the next
+    // chunk's weights in flight while the current one is multiplied)
+    {
+        Chunk<INP> ck;
+        ck.load(a.w1h, 0, tid);
+        for (int f0 = 0; f0 < kFH; f0 += 64) {
+            __syncthreads();
+            ck.store(sm.w, SX, tid);
+            __syncthreads();
+            if (f0 + 64 < kFH) ck.load(a.w1h, f0 + 64, tid);
+            f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+            chunk_mfma(sm.xr, SX, sm.w, SX, INP, acc, wave, q, r16);
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int r = 16 * (wave & 1) + 4 * q + e, f = f0 + 16 * (2 * (wave >> 1) + j) + r16;
-                const float z = acc[j][e] + b1[f];
-                const _Float16 h = (_Float16)gelu(z);
-                Z1[r * kFH + f] = z;
-                sm.h1r[r * kSH + f] = h;
-                sm.h1t[f * kST + r] = h;
-            }
+                for (int e = 0; e < 4; ++e) {
+                    const int r = 16 * (wave & 1) + 4 * q + e, f = f0 + 16 * (2 * (wave >> 1) + j) + r16;
+                    const float z = acc[j][e] + b1[f];
+                    const _Float16 h = (_Float16)gelu(z);
+                    Z1[r * kFH + f] = z;
+                    sm.h1r[r * kSH + f] = h;
+                    sm.h1t[f * kST + r] = h;
+                }
+        }
     }
     // layer 2: Z2 = H1 W2^T + b2, fp16(H2) rows into hx
     _Float16 *h2r = sm.hx;
-    for (int f0 = 0; f0 < kFH; f0 += 64) {
-        __syncthreads();
-        stage_rows(sm.w, SW, W2, kFH, f0, kFH, kFH, tid);
-        __syncthreads();
-        f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
-        chunk_mfma(sm.h1r, kSH, sm.w, SW, kFH, acc, wave, q, r16);
+    {
+        Chunk<kFH> ck;
+        ck.load(a.w2h, 0, tid);
+        for (int f0 = 0; f0 < kFH; f0 += 64) {
+            __syncthreads();
+            ck.store(sm.w, SW, tid);
+            __syncthreads();
+            if (f0 + 64 < kFH) ck.load(a.w2h, f0 + 64, tid);
+            f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+            chunk_mfma(sm.h1r, kSH, sm.w, SW, kFH, acc, wave, q, r16);
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int r = 16 * (wave & 1) + 4 * q + e, f = f0 + 16 * (2 * (wave >> 1) + j) + r16;
-                const float z = acc[j][e] + b2[f];
-                Z2[r * kFH + f] = z;
-                h2r[r * kSH + f] = (_Float16)gelu(z);
-            }
+                for (int e = 0; e < 4; ++e) {
+                    const int r = 16 * (wave & 1) + 4 * q + e, f = f0 + 16 * (2 * (wave >> 1) + j) + r16;
+                    const float z = acc[j][e] + b2[f];
+                    Z2[r * kFH + f] = z;
+                    h2r[r * kSH + f] = (_Float16)gelu(z);
+                }
+        }
     }
     __syncthreads();
     // head: y = fp16(H2) . fp16(w3) + b3 (8 lanes per row, lane-order sums), dy, loss
@@ -208,18 +209,21 @@ __global__ __launch_bounds__(kFT) void mlp_fused_kernel(FusedArgs a) {
     {
         const int j = tid;
         const float wj = (float)(_Float16)w3[j];
-        float z2[kFR];                                  // the column's Z2, all loads in flight
-#pragma unroll
-        for (int r = 0; r < kFR; ++r) z2[r] = Z2[r * kFH + j];
         float sb = 0.f, sw = 0.f;
+        for (int r0 = 0; r0 < kFR; r0 += 8) {
+            float z2[8];                                // eight rows of the column's Z2 in flight
 #pragma unroll
-        for (int r = 0; r < kFR; ++r) {
-            const float d = sm.dy[r] * wj * gelu_d(z2[r]);
-            const _Float16 dh = (_Float16)d;
-            sm.d2r[r * kSH + j] = dh;
-            sm.d2t[j * kST + r] = dh;
-            sb += d;
-            sw += sm.dy[r] * (float)h2r[r * kSH + j];
+            for (int u = 0; u < 8; ++u) z2[u] = Z2[(r0 + u) * kFH + j];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int r = r0 + u;
+                const float d = sm.dy[r] * wj * gelu_d(z2[u]);
+                const _Float16 dh = (_Float16)d;
+                sm.d2r[r * kSH + j] = dh;
+                sm.d2t[j * kST + r] = dh;
+                sb += d;
+                sw += sm.dy[r] * (float)h2r[r * kSH + j];
+            }
         }
         gb2[j] = sb;
         gw3[j] = sw;
@@ -243,34 +247,41 @@ __global__ __launch_bounds__(kFT) void mlp_fused_kernel(FusedArgs a) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) gW2[(int64_t)(16 * ti + 4 * q + e) * kFH + 16 * tj + r16] = d[e];
     }
-    // dH1 = dZ2 W2 (W2 staged transposed, 64 input features per chunk), dZ1 = dH1 GELU'(Z1)
+    // dH1 = dZ2 W2 (rows of the transposed W2, 64 input features per chunk), dZ1 = dH1 GELU'(Z1)
     _Float16 *d1t = sm.hx;                              // H2 rows are no longer read
-    for (int c0 = 0; c0 < kFH; c0 += 64) {
-        __syncthreads();
-        stage_cols(sm.w, SW, W2, kFH, c0, tid);
-        __syncthreads();
-        f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
-        chunk_mfma(sm.d2r, kSH, sm.w, SW, kFH, acc, wave, q, r16);
+    {
+        Chunk<kFH> ck;
+        ck.load(a.w2th, 0, tid);
+        for (int c0 = 0; c0 < kFH; c0 += 64) {
+            __syncthreads();
+            ck.store(sm.w, SW, tid);
+            __syncthreads();
+            if (c0 + 64 < kFH) ck.load(a.w2th, c0 + 64, tid);
+            f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+            chunk_mfma(sm.d2r, kSH, sm.w, SW, kFH, acc, wave, q, r16);
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int r = 16 * (wave & 1) + 4 * q + e, i = c0 + 16 * (2 * (wave >> 1) + j) + r16;
-                const float d = acc[j][e] * gelu_d(Z1[r * kFH + i]);
-                Z1[r * kFH + i] = d;                    // dZ1 in place of Z1 (the same thread read it)
-                d1t[i * kST + r] = (_Float16)d;
-            }
+                for (int e = 0; e < 4; ++e) {
+                    const int r = 16 * (wave & 1) + 4 * q + e, i = c0 + 16 * (2 * (wave >> 1) + j) + r16;
+                    const float d = acc[j][e] * gelu_d(Z1[r * kFH + i]);
+                    Z1[r * kFH + i] = d;                // dZ1 in place of Z1 (the same thread read it)
+                    d1t[i * kST + r] = (_Float16)d;
+                }
+        }
     }
     __syncthreads();
     // db1[i] = sum_r dZ1[r][i]
     {
         const int i = tid;
-        float d1[kFR];
-#pragma unroll
-        for (int r = 0; r < kFR; ++r) d1[r] = Z1[r * kFH + i];
         float s = 0.f;
+        for (int r0 = 0; r0 < kFR; r0 += 8) {
+            float d1[8];
 #pragma unroll
-        for (int r = 0; r < kFR; ++r) s += d1[r];
+            for (int u = 0; u < 8; ++u) d1[u] = Z1[(r0 + u) * kFH + i];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += d1[u];
+        }
         gb1[i] = s;
     }
     // dW1[i][c] = sum_r fp16(dZ1[r][i]) fp16(X[r][c])
@@ -287,20 +298,48 @@ __global__ __launch_bounds__(kFT) void mlp_fused_kernel(FusedArgs a) {
     }
 }
 
+// fp16 copies of W1 (rows padded to inp with zeros) and W2 (and its transpose).
+__global__ void mlp_fused_weights_kernel(const float *P, int in, int inp, _Float16 *w1h, _Float16 *w2h,
+                                         _Float16 *w2th) {
+    const float *W1 = P, *W2 = P + (int64_t)kFH * in + kFH;
+    const int n1 = kFH * inp, n2 = kFH * kFH;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n1 + n2; i += gridDim.x * blockDim.x) {
+        if (i < n1) {
+            const int f = i / inp, c = i % inp;
+            w1h[i] = (_Float16)(c < in ? W1[f * in + c] : 0.f);
+        } else {
+            const int j = i - n1, o = j / kFH, c = j % kFH;
+            const _Float16 h = (_Float16)W2[j];
+            w2h[j] = h;
+            w2th[c * kFH + o] = h;
+        }
+    }
+}
+
 // Slice sums in slice order: G = sum_s part[s] (loss: sum_s lossp[s] / B, also
 // hist[*batch]).  With Adam the sum times gscale updates P, M1, M2 at step
-// *step + 1, and the last workgroup to finish advances *step and *batch.
+// *step + 1 (and the fp16 weight copies), and the last workgroup to finish
+// advances *step and *batch.
 __global__ __launch_bounds__(256) void mlp_fused_reduce_kernel(const float *part, const float *lossp, int S,
-                                                               int64_t np, int B, float *G, float *loss, float *hist,
-                                                               int adam, float *P, float *M1, float *M2, float gscale,
-                                                               float lr, int *step, int *batch, unsigned *arrive) {
+                                                               int64_t np, int B, int in, int inp, float *G,
+                                                               float *loss, float *hist, int adam, float *P,
+                                                               float *M1, float *M2, float gscale, float lr,
+                                                               _Float16 *w1h, _Float16 *w2h, _Float16 *w2th,
+                                                               int *step, int *batch, unsigned *arrive) {
     __shared__ unsigned s_last;
     const int t = adam ? *step + 1 : 0;
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     const float c1 = adam ? 1.f - powf(b1, (float)t) : 1.f, c2 = adam ? 1.f - powf(b2, (float)t) : 1.f;
+    const int64_t o2 = (int64_t)kFH * in + kFH, e2 = o2 + (int64_t)kFH * kFH;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
         float g = 0.f;
-        for (int s = 0; s < S; ++s) g += part[(int64_t)s * np + i];
+        for (int s0 = 0; s0 < S; s0 += 16) {           // 16 slice loads in flight, added in slice order
+            float v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = s0 + u < S ? part[(int64_t)(s0 + u) * np + i] : 0.f;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) g += v[u];
+        }
         if (!adam) {
             G[i] = g;
         } else {
@@ -309,7 +348,15 @@ __global__ __launch_bounds__(256) void mlp_fused_reduce_kernel(const float *part
             const float vi = b2 * M2[i] + (1.f - b2) * gi * gi;
             M1[i] = mi;
             M2[i] = vi;
-            P[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+            const float p = P[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+            P[i] = p;
+            if (i < (int64_t)kFH * in) {
+                w1h[(i / in) * inp + i % in] = (_Float16)p;
+            } else if (i >= o2 && i < e2) {
+                const int64_t j = i - o2;
+                w2h[j] = (_Float16)p;
+                w2th[(j % kFH) * kFH + j / kFH] = (_Float16)p;
+            }
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -345,21 +392,33 @@ int mlp_fused_slices(int B) { return (B + kFR - 1) / kFR; }
 
 size_t mlp_fused_zs_floats(int max_batch) { return (size_t)mlp_fused_slices(max_batch) * 2 * kFR * kFH; }
 
+size_t mlp_fused_wh_halfs() { return (size_t)kFH * 128 + 2 * (size_t)kFH * kFH; }
+
+hipError_t mlp_fused_weights(const MlpBuffers &m, hipStream_t s) {
+    if (!mlp_fused_ok(m)) return hipErrorInvalidValue;
+    const int inp = (m.in + 31) / 32 * 32;
+    hipLaunchKernelGGL(mlp_fused_weights_kernel, dim3(256), dim3(256), 0, s, m.P, m.in, inp, m.fwh,
+                       m.fwh + (size_t)kFH * 128, m.fwh + (size_t)kFH * 128 + (size_t)kFH * kFH);
+    return hipGetLastError();
+}
+
 hipError_t mlp_fused_pass(const MlpBuffers &m, int B, const float *X, const float *t, const int *perm, int64_t n,
                           bool adam, float gscale, float lr, float *hist, hipStream_t s) {
     if (!mlp_fused_ok(m) || B < 1 || B > m.max_batch) return hipErrorInvalidValue;
     const int S = mlp_fused_slices(B);
-    FusedArgs a{m.P, X, t, perm, m.batch, n, B, m.in, m.nparams, m.fpart, m.floss, m.fzs, m.bad};
-    hipError_t e;
     const int inp = (m.in + 31) / 32 * 32;
+    _Float16 *w1h = m.fwh, *w2h = w1h + (size_t)kFH * 128, *w2th = w2h + (size_t)kFH * kFH;
+    FusedArgs a{m.P, X, t, perm, m.batch, n, B, m.in, m.nparams, m.fpart, m.floss, m.fzs, w1h, w2h, w2th, m.bad};
+    hipError_t e;
     e = inp == 32 ? launch_fused<32>(a, S, s)
         : inp == 64 ? launch_fused<64>(a, S, s)
         : inp == 96 ? launch_fused<96>(a, S, s)
                     : launch_fused<128>(a, S, s);
     if (e != hipSuccess) return e;
     const int blocks = (int)std::min<int64_t>((m.nparams + 255) / 256, 1024);
-    hipLaunchKernelGGL(mlp_fused_reduce_kernel, dim3(blocks), dim3(256), 0, s, m.fpart, m.floss, S, m.nparams, B, m.G,
-                       m.loss, hist, adam ? 1 : 0, m.P, m.M1, m.M2, gscale, lr, m.step, m.batch, m.farrive);
+    hipLaunchKernelGGL(mlp_fused_reduce_kernel, dim3(blocks), dim3(256), 0, s, m.fpart, m.floss, S, m.nparams, B, m.in,
+                       inp, m.G, m.loss, hist, adam ? 1 : 0, m.P, m.M1, m.M2, gscale, lr, w1h, w2h, w2th, m.step,
+                       m.batch, m.farrive);
     return hipGetLastError();
 }
 
