@@ -17,11 +17,12 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int kFR = 32;                 // rows per slice (one workgroup)
+constexpr int kFR = 16;                 // rows per slice (one workgroup)
+constexpr int kFK = 32;                 // k of the row-sum MFMAs (rows kFR .. kFK - 1 are zero)
 constexpr int kFH = 256;                // hidden width of the fused path
 constexpr int kFT = 256;                // threads per workgroup
 constexpr int kSH = kFH + 8;            // row stride (halfs) of [32][256] planes
-constexpr int kST = kFR + 8;            // row stride (halfs) of transposed [256][32] planes
+constexpr int kST = kFK + 8;            // row stride (halfs) of transposed [256][32] planes
 
 __device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.f + erff(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_d(float x) {
@@ -45,20 +46,15 @@ struct FusedArgs {
     int *bad;
 };
 
-// C[32 x 64] += A[32 x K] B[64 x K]^T, A and B FP16 in LDS with k contiguous
-// (row strides sa, sb); wave w owns row tile w & 1 and column tiles
-// 2 (w >> 1), 2 (w >> 1) + 1; item e of acc[j] is row 16 (w & 1) + 4 q + e,
-// column 16 (2 (w >> 1) + j) + r16 of the chunk.
-__device__ __forceinline__ void chunk_mfma(const _Float16 *A, int sa, const _Float16 *B, int sb, int K, f4 acc[2],
+// C[16 x 64] += A[16 x K] B[64 x K]^T, A and B FP16 in LDS with k contiguous
+// (row strides sa, sb); wave w owns column tile w; item e of acc is row 4 q + e,
+// column 16 w + r16 of the chunk.
+__device__ __forceinline__ void chunk_mfma(const _Float16 *A, int sa, const _Float16 *B, int sb, int K, f4 &acc,
                                            int wave, int q, int r16) {
-    const int rt = wave & 1, ct = 2 * (wave >> 1);
     for (int kk = 0; kk < K; kk += 32) {
-        const h8 a = *reinterpret_cast<const h8 *>(A + (16 * rt + r16) * sa + kk + 8 * q);
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const h8 b = *reinterpret_cast<const h8 *>(B + (16 * (ct + j) + r16) * sb + kk + 8 * q);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc[j], 0, 0, 0);
-        }
+        const h8 a = *reinterpret_cast<const h8 *>(A + r16 * sa + kk + 8 * q);
+        const h8 b = *reinterpret_cast<const h8 *>(B + (16 * wave + r16) * sb + kk + 8 * q);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc, 0, 0, 0);
     }
 }
 
@@ -130,6 +126,20 @@ __global__ __launch_bounds__(kFT) void mlp_fused_kernel(FusedArgs a) {
         sm.src[tid] = (int)s;
         sm.tgt[tid] = s >= 0 ? a.t[s] : 0.f;
     }
+    // rows kFR .. kFK - 1 of the transposed planes are zero (k padding of the row sums)
+    {
+        const uint4 z = uint4{0u, 0u, 0u, 0u};
+        for (int i = tid; i < kFH; i += kFT) {
+            *reinterpret_cast<uint4 *>(sm.h1t + i * kST + kFR) = z;
+            *reinterpret_cast<uint4 *>(sm.h1t + i * kST + kFR + 8) = z;
+            *reinterpret_cast<uint4 *>(sm.d2t + i * kST + kFR) = z;
+            *reinterpret_cast<uint4 *>(sm.d2t + i * kST + kFR + 8) = z;
+        }
+        for (int i = tid; i < INP; i += kFT) {
+            *reinterpret_cast<uint4 *>(sm.xt + i * kST + kFR) = z;
+            *reinterpret_cast<uint4 *>(sm.xt + i * kST + kFR + 8) = z;
+        }
+    }
     __syncthreads();
     // X rows and their transpose (zero past the slice's rows and past in)
     for (int it = tid; it < kFR * INP; it += kFT) {
@@ -150,14 +160,12 @@ __global__ __launch_bounds__(kFT) void mlp_fused_kernel(FusedArgs a) {
             ck.store(sm.w, SX, tid);
             __syncthreads();
             if (f0 + 64 < kFH) ck.load(a.w1h, f0 + 64, tid);
-            f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+            f4 acc = f4{0.f, 0.f, 0.f, 0.f};
             chunk_mfma(sm.xr, SX, sm.w, SX, INP, acc, wave, q, r16);
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int r = 16 * (wave & 1) + 4 * q + e, f = f0 + 16 * (2 * (wave >> 1) + j) + r16;
-                    const float z = acc[j][e] + b1[f];
+                    const int r = 4 * q + e, f = f0 + 16 * wave + r16;
+                    const float z = acc[e] + b1[f];
                     const _Float16 h = (_Float16)gelu(z);
                     Z1[r * kFH + f] = z;
                     sm.h1r[r * kSH + f] = h;
@@ -175,29 +183,28 @@ __global__ __launch_bounds__(kFT) void mlp_fused_kernel(FusedArgs a) {
             ck.store(sm.w, SW, tid);
             __syncthreads();
             if (f0 + 64 < kFH) ck.load(a.w2h, f0 + 64, tid);
-            f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+            f4 acc = f4{0.f, 0.f, 0.f, 0.f};
             chunk_mfma(sm.h1r, kSH, sm.w, SW, kFH, acc, wave, q, r16);
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int r = 16 * (wave & 1) + 4 * q + e, f = f0 + 16 * (2 * (wave >> 1) + j) + r16;
-                    const float z = acc[j][e] + b2[f];
+                    const int r = 4 * q + e, f = f0 + 16 * wave + r16;
+                    const float z = acc[e] + b2[f];
                     Z2[r * kFH + f] = z;
                     h2r[r * kSH + f] = (_Float16)gelu(z);
                 }
         }
     }
     __syncthreads();
-    // head: y = fp16(H2) . fp16(w3) + b3 (8 lanes per row, lane-order sums), dy, loss
+    // head: y = fp16(H2) . fp16(w3) + b3 (16 lanes per row, lane-order sums), dy, loss
     {
-        const int r = tid >> 3, l8 = tid & 7;
+        const int r = tid >> 4, l16 = tid & 15;
         float s = 0.f;
-        for (int j = l8; j < kFH; j += 8) s += (float)h2r[r * kSH + j] * (float)(_Float16)w3[j];
+        for (int j = l16; j < kFH; j += 16) s += (float)h2r[r * kSH + j] * (float)(_Float16)w3[j];
         s += __shfl_xor(s, 1);
         s += __shfl_xor(s, 2);
         s += __shfl_xor(s, 4);
-        if (l8 == 0) {
+        s += __shfl_xor(s, 8);
+        if (l16 == 0) {
             const float yb = s + b3[0];
             const bool ok = r < rows;
             sm.dy[r] = ok ? 2.f * (yb - sm.tgt[r]) : 0.f;
@@ -249,6 +256,10 @@ __global__ __launch_bounds__(kFT) void mlp_fused_kernel(FusedArgs a) {
     }
     // dH1 = dZ2 W2 (rows of the transposed W2, 64 input features per chunk), dZ1 = dH1 GELU'(Z1)
     _Float16 *d1t = sm.hx;                              // H2 rows are no longer read
+    for (int i = tid; i < kFH; i += kFT) {              // its k padding (H2 rows lay there)
+        *reinterpret_cast<uint4 *>(d1t + i * kST + kFR) = uint4{0u, 0u, 0u, 0u};
+        *reinterpret_cast<uint4 *>(d1t + i * kST + kFR + 8) = uint4{0u, 0u, 0u, 0u};
+    }
     {
         Chunk<kFH> ck;
         ck.load(a.w2th, 0, tid);
@@ -257,14 +268,12 @@ __global__ __launch_bounds__(kFT) void mlp_fused_kernel(FusedArgs a) {
             ck.store(sm.w, SW, tid);
             __syncthreads();
             if (c0 + 64 < kFH) ck.load(a.w2th, c0 + 64, tid);
-            f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+            f4 acc = f4{0.f, 0.f, 0.f, 0.f};
             chunk_mfma(sm.d2r, kSH, sm.w, SW, kFH, acc, wave, q, r16);
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int r = 16 * (wave & 1) + 4 * q + e, i = c0 + 16 * (2 * (wave >> 1) + j) + r16;
-                    const float d = acc[j][e] * gelu_d(Z1[r * kFH + i]);
+                    const int r = 4 * q + e, i = c0 + 16 * wave + r16;
+                    const float d = acc[e] * gelu_d(Z1[r * kFH + i]);
                     Z1[r * kFH + i] = d;                // dZ1 in place of Z1 (the same thread read it)
                     d1t[i * kST + r] = (_Float16)d;
                 }
