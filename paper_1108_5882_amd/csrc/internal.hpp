@@ -291,7 +291,7 @@ hipError_t mlp_pass(const MlpBuffers &m, int B, const float *Xb, const float *tb
                     hipStream_t s);
 hipError_t mlp_scale(const float *x, int64_t n, float scale, float *out, hipStream_t s);
 // Fused training pass (mlp_fused.hip), hidden width 256 and in <= 128 only: per
-// slice of 32 rows (X rows perm[*m.batch B + r] when perm is set, else rows
+// slice of 16 rows (X rows perm[*m.batch B + r] when perm is set, else rows
 // 0 .. B-1) the forward pass, loss and gradient sums, then the slices added in
 // order into m.G and m.loss (hist[*m.batch] too when set); with adam, Adam on
 // m.P with m.G * gscale at step *m.step + 1 instead of writing m.G, and

@@ -1,12 +1,12 @@
 // Fused training pass of the surrogate network at hidden width 256: one
-// launch computes, per slice of 32 mini-batch rows, the forward pass, the
+// launch computes, per slice of 16 mini-batch rows, the forward pass, the
 // loss and every parameter gradient of the slice; a second launch adds the
 // slices in order and applies Adam (or returns the summed gradient).  The
 // arithmetic is that of the layer-by-layer kernels in mlp.hip: every matrix
 // product rounds both operands to FP16 and accumulates in FP32
 // (v_mfma_f32_16x16x32_f16), biases and activations are FP32, the head and
 // the weight-3 gradient use the FP16-rounded activations.  Only the order in
-// which the rows of a mini-batch are added differs (slices of 32 rows, added
+// which the rows of a mini-batch are added differs (slices of 16 rows, added
 // in slice order).
 #include "internal.hpp"
 
@@ -16,6 +16,7 @@ namespace {
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef unsigned u4 __attribute__((ext_vector_type(4)));   // a register array of these stays in registers
 
 constexpr int kFR = 16;                 // rows per slice (one workgroup)
 constexpr int kFK = 32;                 // k of the row-sum MFMAs (rows kFR .. kFK - 1 are zero)
@@ -63,19 +64,19 @@ __device__ __forceinline__ void chunk_mfma(const _Float16 *A, int sa, const _Flo
 template <int W>
 struct Chunk {
     static constexpr int N = 64 * W / 8 / kFT;          // 16-byte pieces per thread
-    uint4 v[N];
+    u4 v[N];
     __device__ __forceinline__ void load(const _Float16 *src, int r0, int tid) {
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             const int it = tid + i * kFT, r = it / (W / 8), c = 8 * (it % (W / 8));
-            v[i] = *reinterpret_cast<const uint4 *>(src + (int64_t)(r0 + r) * W + c);
+            v[i] = *reinterpret_cast<const u4 *>(src + (int64_t)(r0 + r) * W + c);
         }
     }
     __device__ __forceinline__ void store(_Float16 *dst, int sd, int tid) const {
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             const int it = tid + i * kFT, r = it / (W / 8), c = 8 * (it % (W / 8));
-            *reinterpret_cast<uint4 *>(dst + r * sd + c) = v[i];
+            *reinterpret_cast<u4 *>(dst + r * sd + c) = v[i];
         }
     }
 };
@@ -95,7 +96,7 @@ struct FusedSmem {
     int src[kFR];
 };
 
-// One workgroup per slice of 32 rows.
+// One workgroup per slice of 16 rows.
 template <int INP>
 __global__ __launch_bounds__(kFT) void mlp_fused_kernel(FusedArgs a) {
     static_assert(kFR * kSH <= kFH * kST, "H2 rows must fit in the dZ1 plane");
@@ -128,16 +129,16 @@ __global__ __launch_bounds__(kFT) void mlp_fused_kernel(FusedArgs a) {
     }
     // rows kFR .. kFK - 1 of the transposed planes are zero (k padding of the row sums)
     {
-        const uint4 z = uint4{0u, 0u, 0u, 0u};
+        const u4 z = u4{0u, 0u, 0u, 0u};
         for (int i = tid; i < kFH; i += kFT) {
-            *reinterpret_cast<uint4 *>(sm.h1t + i * kST + kFR) = z;
-            *reinterpret_cast<uint4 *>(sm.h1t + i * kST + kFR + 8) = z;
-            *reinterpret_cast<uint4 *>(sm.d2t + i * kST + kFR) = z;
-            *reinterpret_cast<uint4 *>(sm.d2t + i * kST + kFR + 8) = z;
+            *reinterpret_cast<u4 *>(sm.h1t + i * kST + kFR) = z;
+            *reinterpret_cast<u4 *>(sm.h1t + i * kST + kFR + 8) = z;
+            *reinterpret_cast<u4 *>(sm.d2t + i * kST + kFR) = z;
+            *reinterpret_cast<u4 *>(sm.d2t + i * kST + kFR + 8) = z;
         }
         for (int i = tid; i < INP; i += kFT) {
-            *reinterpret_cast<uint4 *>(sm.xt + i * kST + kFR) = z;
-            *reinterpret_cast<uint4 *>(sm.xt + i * kST + kFR + 8) = z;
+            *reinterpret_cast<u4 *>(sm.xt + i * kST + kFR) = z;
+            *reinterpret_cast<u4 *>(sm.xt + i * kST + kFR + 8) = z;
         }
     }
     __syncthreads();
@@ -257,8 +258,8 @@ __global__ __launch_bounds__(kFT) void mlp_fused_kernel(FusedArgs a) {
     // dH1 = dZ2 W2 (rows of the transposed W2, 64 input features per chunk), dZ1 = dH1 GELU'(Z1)
     _Float16 *d1t = sm.hx;                              // H2 rows are no longer read
     for (int i = tid; i < kFH; i += kFT) {              // its k padding (H2 rows lay there)
-        *reinterpret_cast<uint4 *>(d1t + i * kST + kFR) = uint4{0u, 0u, 0u, 0u};
-        *reinterpret_cast<uint4 *>(d1t + i * kST + kFR + 8) = uint4{0u, 0u, 0u, 0u};
+        *reinterpret_cast<u4 *>(d1t + i * kST + kFR) = u4{0u, 0u, 0u, 0u};
+        *reinterpret_cast<u4 *>(d1t + i * kST + kFR + 8) = u4{0u, 0u, 0u, 0u};
     }
     {
         Chunk<kFH> ck;
