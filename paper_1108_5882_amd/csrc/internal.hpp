@@ -274,7 +274,7 @@ struct MlpBuffers {
     // fused path (hidden width 256): per-slice gradient sums and losses, Z scratch, arrival counter
     float *fpart = nullptr, *floss = nullptr, *fzs = nullptr;
     _Float16 *fwh = nullptr;          // fp16 W1 [256][128], W2 [256][256], W2^T [256][256]
-    unsigned *farrive = nullptr;
+    int *ftnext = nullptr;            // Adam step of the pending update (device)
 };
 
 int64_t mlp_param_count(int in, int hidden);

@@ -144,7 +144,7 @@ pwa_status pwa_mlp_create(pwa_mlp **out, int device, int32_t in, int32_t hidden,
     b.step = ints;
     b.batch = ints + 1;
     b.bad = ints + 2;
-    b.farrive = reinterpret_cast<unsigned *>(ints + 3);
+    b.ftnext = ints + 3;
     if (hidden == 256 && in <= 128) {   // buffers of the fused training pass
         const size_t S = (size_t)mlp_fused_slices(max_batch);
         if ((st = alloc(m, &b.fpart, S * (size_t)b.nparams)) || (st = alloc(m, &b.floss, S)) ||

@@ -35,6 +35,8 @@ struct FusedArgs {
     const float *X, *t;                 // features [n][in] and targets [n]
     const int *perm;                    // null: rows 0 .. B-1 of X; else rows perm[*batch B + r]
     const int *batch;                   // mini-batch index (with perm)
+    const int *step;                    // Adam steps taken
+    int *tnext;                         // the step the following Adam update makes (*step + 1)
     int64_t n;
     int B, in;
     int64_t nparams;
@@ -113,6 +115,7 @@ __global__ __launch_bounds__(kFT) void mlp_fused_kernel(FusedArgs a) {
     float *Z1 = a.zs + (int64_t)slice * 2 * kFR * kFH, *Z2 = Z1 + kFR * kFH;
     const int rows = a.B - slice * kFR < kFR ? a.B - slice * kFR : kFR;
 
+    if (slice == 0 && tid == 0) *a.tnext = *a.step + 1;   // for the Adam update of this pass
     // rows of the slice (a bad permutation entry reads row 0 and raises the flag)
     if (tid < kFR) {
         int64_t s = -1;
@@ -328,27 +331,26 @@ __global__ void mlp_fused_weights_kernel(const float *P, int in, int inp, _Float
 
 // Slice sums in slice order: G = sum_s part[s] (loss: sum_s lossp[s] / B, also
 // hist[*batch]).  With Adam the sum times gscale updates P, M1, M2 at step
-// *step + 1 (and the fp16 weight copies), and the last workgroup to finish
-// advances *step and *batch.
+// *tnext (written by the slice pass) and the fp16 weight copies; workgroup 0
+// then advances *step and *batch (no other workgroup reads them).
 __global__ __launch_bounds__(256) void mlp_fused_reduce_kernel(const float *part, const float *lossp, int S,
                                                                int64_t np, int B, int in, int inp, float *G,
                                                                float *loss, float *hist, int adam, float *P,
                                                                float *M1, float *M2, float gscale, float lr,
                                                                _Float16 *w1h, _Float16 *w2h, _Float16 *w2th,
-                                                               int *step, int *batch, unsigned *arrive) {
-    __shared__ unsigned s_last;
-    const int t = adam ? *step + 1 : 0;
+                                                               const int *tnext, int *step, int *batch) {
+    const int t = adam ? *tnext : 0;
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     const float c1 = adam ? 1.f - powf(b1, (float)t) : 1.f, c2 = adam ? 1.f - powf(b2, (float)t) : 1.f;
     const int64_t o2 = (int64_t)kFH * in + kFH, e2 = o2 + (int64_t)kFH * kFH;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
         float g = 0.f;
-        for (int s0 = 0; s0 < S; s0 += 16) {           // 16 slice loads in flight, added in slice order
-            float v[16];
+        for (int s0 = 0; s0 < S; s0 += 32) {           // 32 slice loads in flight, added in slice order
+            float v[32];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) v[u] = s0 + u < S ? part[(int64_t)(s0 + u) * np + i] : 0.f;
+            for (int u = 0; u < 32; ++u) v[u] = s0 + u < S ? part[(int64_t)(s0 + u) * np + i] : 0.f;
 #pragma unroll
-            for (int u = 0; u < 16; ++u) g += v[u];
+            for (int u = 0; u < 32; ++u) g += v[u];
         }
         if (!adam) {
             G[i] = g;
@@ -374,17 +376,10 @@ __global__ __launch_bounds__(256) void mlp_fused_reduce_kernel(const float *part
         for (int s = 0; s < S; ++s) l += lossp[s];
         *loss = l / (float)B;
         if (hist) hist[*batch] = l / (float)B;
-    }
-    if (!adam) return;
-    // every workgroup has used *step (and block 0 *batch) before it arrives: the
-    // last one to arrive advances them
-    __syncthreads();
-    if (threadIdx.x == 0) s_last = atomicAdd(arrive, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (s_last && threadIdx.x == 0) {
-        *step += 1;
-        *batch += 1;
-        *arrive = 0u;
+        if (adam) {
+            *step = t;
+            *batch += 1;
+        }
     }
 }
 
@@ -418,7 +413,8 @@ hipError_t mlp_fused_pass(const MlpBuffers &m, int B, const float *X, const floa
     const int S = mlp_fused_slices(B);
     const int inp = (m.in + 31) / 32 * 32;
     _Float16 *w1h = m.fwh, *w2h = w1h + (size_t)kFH * 128, *w2th = w2h + (size_t)kFH * kFH;
-    FusedArgs a{m.P, X, t, perm, m.batch, n, B, m.in, m.nparams, m.fpart, m.floss, m.fzs, w1h, w2h, w2th, m.bad};
+    FusedArgs a{m.P, X, t, perm, m.batch, m.step, m.ftnext, n, B, m.in, m.nparams, m.fpart, m.floss, m.fzs, w1h, w2h,
+                w2th, m.bad};
     hipError_t e;
     e = inp == 32 ? launch_fused<32>(a, S, s)
         : inp == 64 ? launch_fused<64>(a, S, s)
@@ -427,8 +423,8 @@ hipError_t mlp_fused_pass(const MlpBuffers &m, int B, const float *X, const floa
     if (e != hipSuccess) return e;
     const int blocks = (int)std::min<int64_t>((m.nparams + 255) / 256, 1024);
     hipLaunchKernelGGL(mlp_fused_reduce_kernel, dim3(blocks), dim3(256), 0, s, m.fpart, m.floss, S, m.nparams, B, m.in,
-                       inp, m.G, m.loss, hist, adam ? 1 : 0, m.P, m.M1, m.M2, gscale, lr, w1h, w2h, w2th, m.step,
-                       m.batch, m.farrive);
+                       inp, m.G, m.loss, hist, adam ? 1 : 0, m.P, m.M1, m.M2, gscale, lr, w1h, w2h, w2th, m.ftnext,
+                       m.step, m.batch);
     return hipGetLastError();
 }
 
