@@ -78,10 +78,13 @@ def _blocks(n_in, hidden):
     return out
 
 
-@pytest.mark.parametrize("B", [1, 300, 1024])
-def test_forward_and_gradient_match_oracle(pwa, torch, B):
-    n_in, hidden = 32, 256
-    _say(f"case mlp loss_grad B={B}")
+@pytest.mark.parametrize("B,hidden,n_in", [(1, 256, 32), (300, 256, 32), (1024, 256, 32), (300, 128, 32),
+                                           (77, 256, 10), (130, 256, 40)])
+def test_forward_and_gradient_match_oracle(pwa, torch, B, hidden, n_in):
+    """Hidden width 256 runs the fused pass (16-row slices, ragged last slice at
+    B = 300, 77 and 130; input widths padded to 32 or 64); other widths the
+    layer-by-layer kernels."""
+    _say(f"case mlp loss_grad B={B} hidden={hidden} in={n_in}")
     P = synth.mlp_init(n_in, hidden, seed=B)
     g = np.random.default_rng(B)
     X = OM.features(synth.draw_v(g, B, n_in // 2)).astype(np.float32)
@@ -144,9 +147,11 @@ def test_predict_at_screening_size(pwa, torch):
     assert np.array_equal(idx, OM.topk(y, 256))
 
 
-def test_adam_steps_match_oracle(pwa, torch):
-    """Two training steps (same batch) against the oracle's Adam from the kernel's own gradients."""
-    n_in, hidden, B = 32, 256, 512
+@pytest.mark.parametrize("hidden", [256, 128])
+def test_adam_steps_match_oracle(pwa, torch, hidden):
+    """Two training steps (same batch) against the oracle's Adam from the kernel's own
+    gradients (fused pass at width 256, layer-by-layer kernels at 128)."""
+    n_in, B = 32, 512
     P0 = synth.mlp_init(n_in, hidden, seed=11)
     g = np.random.default_rng(11)
     X = OM.features(synth.draw_v(g, B, 16)).astype(np.float32)
