@@ -271,8 +271,8 @@ struct MlpBuffers {
     float *Xb, *tb;                   // gathered mini-batch features and targets
     float *ws;                        // reduction workspace, mlp_workspace_floats(in, hidden) floats
     int *step, *batch, *bad;          // Adam step count, mini-batch index, bad-index flag (device)
-    // fused path (hidden width 256): per-slice gradient sums and losses, Z scratch, arrival counter
-    float *fpart = nullptr, *floss = nullptr, *fzs = nullptr;
+    // fused path (hidden width 256): per-slice gradient sums and losses
+    float *fpart = nullptr, *floss = nullptr;
     _Float16 *fwh = nullptr;          // fp16 W1 [256][128], W2 [256][256], W2^T [256][256]
     int *ftnext = nullptr;            // Adam step of the pending update (device)
 };
@@ -298,7 +298,6 @@ hipError_t mlp_scale(const float *x, int64_t n, float scale, float *out, hipStre
 // *m.step, *m.batch advanced.
 bool mlp_fused_ok(const MlpBuffers &m);
 int mlp_fused_slices(int B);
-size_t mlp_fused_zs_floats(int max_batch);
 size_t mlp_fused_wh_halfs();
 // fp16 copies of the current weights for the fused pass (after any change of m.P
 // other than the fused pass's own Adam steps)

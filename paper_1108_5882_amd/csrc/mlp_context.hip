@@ -148,7 +148,6 @@ pwa_status pwa_mlp_create(pwa_mlp **out, int device, int32_t in, int32_t hidden,
     if (hidden == 256 && in <= 128) {   // buffers of the fused training pass
         const size_t S = (size_t)mlp_fused_slices(max_batch);
         if ((st = alloc(m, &b.fpart, S * (size_t)b.nparams)) || (st = alloc(m, &b.floss, S)) ||
-            (st = alloc(m, &b.fzs, mlp_fused_zs_floats(max_batch))) ||
             (st = alloc(m, &b.fwh, mlp_fused_wh_halfs()))) {
             g_lerr = m->err;
             pwa_mlp_destroy(m);

@@ -42,7 +42,6 @@ struct FusedArgs {
     int64_t nparams;
     float *part;                        // [slice][nparams] gradient sums of the slice's rows
     float *lossp;                       // [slice] sum of the squared errors
-    float *zs;                          // [slice][2][32][256] Z1 then Z2 (FP32)
     const _Float16 *w1h;                // fp16(W1) [256][INP] (zero past in)
     const _Float16 *w2h;                // fp16(W2) [256][256]
     const _Float16 *w2th;               // fp16(W2) transposed [256][256]
@@ -94,6 +93,8 @@ struct FusedSmem {
     _Float16 d2t[kFH * kST];            // fp16(dZ2), transposed
     _Float16 hx[kFH * kST];             // fp16(H2) rows (first kFR * kSH), later fp16(dZ1) transposed
     _Float16 w[64 * (kFH + 8 > INP + 8 ? kFH + 8 : INP + 8)];   // one staged 64-row weight chunk
+    float z1[kFR * kFH];                // Z1, later dZ1 (FP32)
+    float z2[kFR * kFH];                // Z2 (FP32)
     float tgt[kFR], dy[kFR], lrow[kFR];
     int src[kFR];
 };
@@ -112,7 +113,7 @@ __global__ __launch_bounds__(kFT) void mlp_fused_kernel(FusedArgs a) {
     float *G = a.part + (int64_t)slice * a.nparams;
     float *gW1 = G, *gb1 = gW1 + (int64_t)kFH * in, *gW2 = gb1 + kFH, *gb2 = gW2 + (int64_t)kFH * kFH,
           *gw3 = gb2 + kFH, *gb3 = gw3 + kFH;
-    float *Z1 = a.zs + (int64_t)slice * 2 * kFR * kFH, *Z2 = Z1 + kFR * kFH;
+    float *Z1 = sm.z1, *Z2 = sm.z2;
     const int rows = a.B - slice * kFR < kFR ? a.B - slice * kFR : kFR;
 
     if (slice == 0 && tid == 0) *a.tnext = *a.step + 1;   // for the Adam update of this pass
@@ -222,7 +223,7 @@ __global__ __launch_bounds__(kFT) void mlp_fused_kernel(FusedArgs a) {
         const float wj = (float)(_Float16)w3[j];
         float sb = 0.f, sw = 0.f;
         for (int r0 = 0; r0 < kFR; r0 += 8) {
-            float z2[8];                                // eight rows of the column's Z2 in flight
+            float z2[8];                                // eight rows of the column's Z2
 #pragma unroll
             for (int u = 0; u < 8; ++u) z2[u] = Z2[(r0 + u) * kFH + j];
 #pragma unroll
@@ -395,8 +396,6 @@ bool mlp_fused_ok(const MlpBuffers &m) { return m.hidden == kFH && m.in >= 1 && 
 
 int mlp_fused_slices(int B) { return (B + kFR - 1) / kFR; }
 
-size_t mlp_fused_zs_floats(int max_batch) { return (size_t)mlp_fused_slices(max_batch) * 2 * kFR * kFH; }
-
 size_t mlp_fused_wh_halfs() { return (size_t)kFH * 128 + 2 * (size_t)kFH * kFH; }
 
 hipError_t mlp_fused_weights(const MlpBuffers &m, hipStream_t s) {
@@ -413,8 +412,8 @@ hipError_t mlp_fused_pass(const MlpBuffers &m, int B, const float *X, const floa
     const int S = mlp_fused_slices(B);
     const int inp = (m.in + 31) / 32 * 32;
     _Float16 *w1h = m.fwh, *w2h = w1h + (size_t)kFH * 128, *w2th = w2h + (size_t)kFH * kFH;
-    FusedArgs a{m.P, X, t, perm, m.batch, m.step, m.ftnext, n, B, m.in, m.nparams, m.fpart, m.floss, m.fzs, w1h, w2h,
-                w2th, m.bad};
+    FusedArgs a{m.P, X, t, perm, m.batch, m.step, m.ftnext, n, B, m.in, m.nparams, m.fpart, m.floss, w1h, w2h, w2th,
+                m.bad};
     hipError_t e;
     e = inp == 32 ? launch_fused<32>(a, S, s)
         : inp == 64 ? launch_fused<64>(a, S, s)
