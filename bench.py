@@ -162,7 +162,7 @@ def main():
         cfg = ctx.stream_cfg()
         log(f"stream configuration {cfg} (given)")
     else:
-        cfg, tune_ms = ctx.autotune(reps=5)
+        cfg, tune_ms = ctx.autotune(reps=20)
         log(f"autotuned stream configuration {cfg}: {tune_ms * 1e3:.1f} us")
     for _ in range(args.warmup):
         ctx.nll_grad(V)

@@ -292,7 +292,7 @@ pwa_status pwa_set_stream_cfg(pwa_ctx *ctx, const pwa_stream_cfg *cfg);
 /* Autotuner: times every compiled configuration of the current layout width
  * (and blocks_per_cu in {2, 3, 4, 6, 8, 12, 16}) on the samples currently set,
  * `reps` evaluations each (the pass over the rows and the combine of its
- * block partials) after one warm-up, keeps the fastest (of those within 2% of
+ * block partials) after one warm-up, keeps the fastest (of those within 1% of
  * it, the one with the fewest blocks per CU, then rows per stage, then lanes
  * per row, so that tuning the same shapes again settles on one configuration)
  * in the context and

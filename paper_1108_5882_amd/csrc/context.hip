@@ -1117,7 +1117,7 @@ pwa_status pwa_autotune(pwa_ctx *ctx, int32_t reps, pwa_stream_cfg *best, double
             timed.emplace_back(ctx->cfg, ms / reps);
         }
     }
-    // the fastest, except that among the configurations within 2% of it the
+    // the fastest, except that among the configurations within 1% of it the
     // one with the fewest blocks per CU, then rows per stage, then lanes per
     // row is kept, so that tuning the same shapes again settles on the same
     // configuration despite run-to-run noise
@@ -1128,7 +1128,7 @@ pwa_status pwa_autotune(pwa_ctx *ctx, int32_t reps, pwa_stream_cfg *best, double
     bool have = false;
     double chosen_t = best_t;
     for (const auto &ct : timed) {
-        if (ct.second > 1.02 * best_t) continue;
+        if (ct.second > 1.01 * best_t) continue;
         if (!have || key(ct.first) < key(best_cfg)) {
             best_cfg = ct.first;
             chosen_t = ct.second;
