@@ -494,8 +494,8 @@ pwa_status pwa_mlp_loss_grad(pwa_mlp *m, const float *X, const float *t, int32_t
 /* nsteps Adam steps with learning rate lr; step s uses the rows
  * perm[s * batch .. s * batch + batch - 1] of X [n][in] and t[n] (perm: int32
  * device array of nsteps * batch entries in [0, n); the random order is the
- * caller's).  One step (gather, forward, backward, Adam) is captured in a HIP
- * graph and replayed.  loss_hist (device, nsteps floats, or NULL) receives
+ * caller's).  One step (gather, forward, backward, Adam) and a group of 16
+ * steps are captured in HIP graphs and replayed (whole groups first).  loss_hist (device, nsteps floats, or NULL) receives
  * each step's batch loss; avg_ms (host, optional) the time per step.
  * PWA_E_INVAL after the run if some perm entry was out of range (row 0 was
  * used in its place). */

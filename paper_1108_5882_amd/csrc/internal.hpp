@@ -271,8 +271,10 @@ struct MlpBuffers {
     float *Xb, *tb;                   // gathered mini-batch features and targets
     float *ws;                        // reduction workspace, mlp_workspace_floats(in, hidden) floats
     int *step, *batch, *bad;          // Adam step count, mini-batch index, bad-index flag (device)
-    // fused path (hidden width 256): per-slice gradient sums and losses
-    float *fpart = nullptr, *floss = nullptr;
+    // fused path (hidden width 256): the row pass's FP16 planes (H1, dZ2, dZ1, X
+    // transposed) and per-slice vector sums
+    _Float16 *fact = nullptr;
+    float *fvec = nullptr;
     _Float16 *fwh = nullptr;          // fp16 W1 [256][128], W2 [256][256], W2^T [256][256]
     int *ftnext = nullptr;            // Adam step of the pending update (device)
 };
@@ -292,13 +294,15 @@ hipError_t mlp_pass(const MlpBuffers &m, int B, const float *Xb, const float *tb
 hipError_t mlp_scale(const float *x, int64_t n, float scale, float *out, hipStream_t s);
 // Fused training pass (mlp_fused.hip), hidden width 256 and in <= 128 only: per
 // slice of 16 rows (X rows perm[*m.batch B + r] when perm is set, else rows
-// 0 .. B-1) the forward pass, loss and gradient sums, then the slices added in
-// order into m.G and m.loss (hist[*m.batch] too when set); with adam, Adam on
-// m.P with m.G * gscale at step *m.step + 1 instead of writing m.G, and
-// *m.step, *m.batch advanced.
+// 0 .. B-1) the forward pass, loss and activation gradients, then the weight
+// gradients over the whole mini-batch into m.G and m.loss (hist[*m.batch] too
+// when set); with adam, Adam on m.P with m.G * gscale at step *m.step + 1
+// instead of writing m.G, and *m.step, *m.batch advanced.
 bool mlp_fused_ok(const MlpBuffers &m);
 int mlp_fused_slices(int B);
 size_t mlp_fused_wh_halfs();
+size_t mlp_fused_act_halfs(int max_batch);
+size_t mlp_fused_vec_floats(int max_batch);
 // fp16 copies of the current weights for the fused pass (after any change of m.P
 // other than the fused pass's own Adam steps)
 hipError_t mlp_fused_weights(const MlpBuffers &m, hipStream_t s);

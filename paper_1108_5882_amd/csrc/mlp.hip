@@ -10,8 +10,8 @@
 // and used in FP16 by the matrix cores; every GEMM rounds both operands to
 // FP16 when they are staged and accumulates in FP32 (v_mfma_f32_16x16x32_f16).
 // Loss: mean squared error.  Optimiser: Adam (0.9, 0.999, 1e-8) on the FP32
-// master weights.  Every kernel of a training step is captured in a HIP graph
-// and replayed per mini-batch.
+// master weights.  The kernels of a training step are captured in HIP graphs
+// (one step, and groups of 16 steps) and replayed.
 #include "internal.hpp"
 
 #include <cmath>

@@ -1,5 +1,5 @@
 // C ABI of the NLL surrogate network: device buffers, parameter I/O, the
-// training step captured in a HIP graph, chunked inference and top-k
+// training steps captured in HIP graphs (one step, and groups of 16), chunked inference and top-k
 // selection.  Every entry point orders its work on the object's stream and
 // waits for it before returning.
 #include <hip/hip_runtime.h>
@@ -25,8 +25,8 @@ struct pwa_mlp {
     float *tk_key[2] = {nullptr, nullptr};
     int *tk_idx[2] = {nullptr, nullptr};
     size_t tk_cap = 0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr, graph_n = nullptr;      // one training step; kGroupSteps steps
+    hipGraphExec_t exec = nullptr, exec_n = nullptr;
     struct Key {
         const float *X, *t;
         int64_t n;
@@ -85,10 +85,41 @@ pwa_status alloc(pwa_mlp *m, T **p, size_t count) {
 }
 
 void drop_graph(pwa_mlp *m) {
-    if (m->exec) (void)hipGraphExecDestroy(m->exec);
-    if (m->graph) (void)hipGraphDestroy(m->graph);
-    m->exec = nullptr;
-    m->graph = nullptr;
+    for (hipGraphExec_t *x : {&m->exec, &m->exec_n}) {
+        if (*x) (void)hipGraphExecDestroy(*x);
+        *x = nullptr;
+    }
+    for (hipGraph_t *g : {&m->graph, &m->graph_n}) {
+        if (*g) (void)hipGraphDestroy(*g);
+        *g = nullptr;
+    }
+}
+
+// Training steps replayed as one graph (the launch gap between graphs is paid
+// once per group).
+constexpr int kGroupSteps = 16;
+
+// count training steps captured into *g and instantiated into *x.
+hipError_t capture_steps(pwa_mlp *m, const float *X, const float *t, int64_t n, const int32_t *perm, int batch,
+                         float lr, float *loss_hist, int count, hipGraph_t *g, hipGraphExec_t *x) {
+    const MlpBuffers &b = m->m;
+    hipError_t e = hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t ec = hipSuccess;
+    for (int i = 0; i < count && ec == hipSuccess; ++i) {
+        if (mlp_fused_ok(b)) {   // two launches: row pass, then weight gradients with Adam
+            ec = mlp_fused_pass(b, batch, X, t, perm, n, true, 1.0f / (float)batch, lr, loss_hist, m->stream);
+        } else {
+            ec = mlp_gather(b, X, t, n, perm, batch, m->stream);
+            if (ec == hipSuccess) ec = mlp_pass(b, batch, b.Xb, b.tb, b.y, true, loss_hist, m->stream);
+            if (ec == hipSuccess) ec = mlp_adam(b, 1.0f / (float)batch, lr, m->stream);
+            if (ec == hipSuccess) ec = mlp_step_inc(b, m->stream);
+        }
+    }
+    e = hipStreamEndCapture(m->stream, g);
+    if (ec != hipSuccess) e = ec;
+    if (e == hipSuccess) e = hipGraphInstantiate(x, *g, nullptr, nullptr, 0);
+    return e;
 }
 
 }  // namespace
@@ -146,8 +177,8 @@ pwa_status pwa_mlp_create(pwa_mlp **out, int device, int32_t in, int32_t hidden,
     b.bad = ints + 2;
     b.ftnext = ints + 3;
     if (hidden == 256 && in <= 128) {   // buffers of the fused training pass
-        const size_t S = (size_t)mlp_fused_slices(max_batch);
-        if ((st = alloc(m, &b.fpart, S * (size_t)b.nparams)) || (st = alloc(m, &b.floss, S)) ||
+        if ((st = alloc(m, &b.fact, mlp_fused_act_halfs(max_batch))) ||
+            (st = alloc(m, &b.fvec, mlp_fused_vec_floats(max_batch))) ||
             (st = alloc(m, &b.fwh, mlp_fused_wh_halfs()))) {
             g_lerr = m->err;
             pwa_mlp_destroy(m);
@@ -268,19 +299,9 @@ pwa_status pwa_mlp_train(pwa_mlp *m, const float *X, const float *t, int64_t n, 
     const pwa_mlp::Key key{X, t, n, perm, batch, lr, loss_hist};
     if (!m->exec || !(m->key == key)) {
         drop_graph(m);
-        L_HIP(m, hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-        hipError_t ec;
-        if (mlp_fused_ok(b)) {   // two launches: slices, then their ordered sum with Adam
-            ec = mlp_fused_pass(b, batch, X, t, perm, n, true, 1.0f / (float)batch, lr, loss_hist, m->stream);
-        } else {
-            ec = mlp_gather(b, X, t, n, perm, batch, m->stream);
-            if (ec == hipSuccess) ec = mlp_pass(b, batch, b.Xb, b.tb, b.y, true, loss_hist, m->stream);
-            if (ec == hipSuccess) ec = mlp_adam(b, 1.0f / (float)batch, lr, m->stream);
-            if (ec == hipSuccess) ec = mlp_step_inc(b, m->stream);
-        }
-        hipError_t e = hipStreamEndCapture(m->stream, &m->graph);
-        if (ec != hipSuccess) e = ec;
-        if (e == hipSuccess) e = hipGraphInstantiate(&m->exec, m->graph, nullptr, nullptr, 0);
+        hipError_t e = capture_steps(m, X, t, n, perm, batch, lr, loss_hist, 1, &m->graph, &m->exec);
+        if (e == hipSuccess)
+            e = capture_steps(m, X, t, n, perm, batch, lr, loss_hist, kGroupSteps, &m->graph_n, &m->exec_n);
         if (e != hipSuccess) {
             drop_graph(m);
             return lfail(m, PWA_E_HIP, "training graph: %s", hipGetErrorString(e));
@@ -299,7 +320,9 @@ pwa_status pwa_mlp_train(pwa_mlp *m, const float *X, const float *t, int64_t n, 
         }
     }
     hipError_t e = avg_ms ? hipEventRecord(e0, m->stream) : hipSuccess;
-    for (int32_t s = 0; s < nsteps && e == hipSuccess; ++s) e = hipGraphLaunch(m->exec, m->stream);
+    int32_t s = 0;
+    for (; s + kGroupSteps <= nsteps && e == hipSuccess; s += kGroupSteps) e = hipGraphLaunch(m->exec_n, m->stream);
+    for (; s < nsteps && e == hipSuccess; ++s) e = hipGraphLaunch(m->exec, m->stream);
     if (e == hipSuccess && avg_ms) e = hipEventRecord(e1, m->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
     if (e == hipSuccess && avg_ms) {

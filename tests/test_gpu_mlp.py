@@ -183,6 +183,33 @@ def test_adam_steps_match_oracle(pwa, torch, hidden):
     assert abs(losses[0].item() - l_or) < 1e-5 * l_or
 
 
+@pytest.mark.parametrize("hidden", [256, 128])
+def test_grouped_steps_equal_single_steps(pwa, torch, hidden):
+    """37 steps in one call (two replays of the 16-step graph, then five of the
+    one-step graph) give bit for bit the parameters and losses of 37 one-step calls."""
+    n_in, B, steps = 32, 64, 37
+    _say(f"case mlp grouped steps hidden={hidden}")
+    P0 = synth.mlp_init(n_in, hidden, seed=21)
+    g = np.random.default_rng(21)
+    X = OM.features(synth.draw_v(g, 4000, 16)).astype(np.float32)
+    t = g.uniform(0, 3, 4000).astype(np.float32)
+    perm = torch.from_numpy(g.permutation(4000)[:steps * B].astype(np.int32)).cuda()
+    Xd, td = torch.from_numpy(X).cuda(), torch.from_numpy(t).cuda()
+    with pwa.Mlp(n_in, hidden, max_batch=B) as m:
+        m.set_params(P0)
+        h1, _ = m.train(Xd, td, perm, B, 1e-3)
+        h1 = h1.cpu().numpy()
+        P1 = m.get_params()
+    with pwa.Mlp(n_in, hidden, max_batch=B) as m:
+        m.set_params(P0)
+        h2 = np.array([m.train(Xd, td, perm[s * B:(s + 1) * B], B, 1e-3)[0].item() for s in range(steps)],
+                      dtype=np.float32)
+        P2 = m.get_params()
+    assert np.array_equal(P1, P2)
+    assert np.array_equal(h1, h2)
+    assert h1[-1] < h1[0]
+
+
 def test_features_targets_select(pwa, torch):
     g = np.random.default_rng(12)
     V = synth.draw_v(g, 5000, 16)
