@@ -224,7 +224,12 @@ __global__ __launch_bounds__(kHThreads) void hess_mfma_kernel(const T *__restric
             constexpr int H = (WPT + 1) / 2;
 #pragma unroll
             for (int w = part == 2 ? 0 : H; w < (part == 2 ? H : WPT); ++w) {
-                const double ar = (double)src[w].x, ai = (double)src[w].y;
+                TP s = src[w];
+                // at large K the amplitudes are converted again here rather than
+                // kept in FP64 from the z sums (twice the registers over the
+                // forming phase); the empty statement hides that the value is the same
+                if constexpr (V_LDS) __asm__ volatile("" : "+v"(s));
+                const double ar = (double)s.x, ai = (double)s.y;
                 xw[4 * w] = fma(ar, ur, -ai * ui);              // Re (A u), column 4 w + sub
                 xw[KP + 4 * w] = fma(ar, ui, ai * ur);          // Im (A u)
             }
@@ -236,7 +241,8 @@ __global__ __launch_bounds__(kHThreads) void hess_mfma_kernel(const T *__restric
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     };
-    // one step: form the step's rows (the next step's loads in flight), then its MFMAs
+    // one step: form the step's rows from cur, load the next step's rows into nxt
+    // (in flight during the MFMAs), then the step's MFMAs
     auto step = [&](const TP (&cur)[WPT], TP (&nxt)[WPT], int64_t b) {
         const bool valid = b + row < r1;
         form(0, cur, X, valid);
@@ -256,14 +262,22 @@ __global__ __launch_bounds__(kHThreads) void hess_mfma_kernel(const T *__restric
             mfma_tiles<NT, T0>(acc, colv, std::make_integer_sequence<int, NTL>{});
         }
     };
-    // two steps per trip so that the two register buffers swap by name
-    TP b0[WPT], b1[WPT];
     int64_t base = r0 + kHRows * wave;
-    fetch(b0, base + row);
-    for (; base < r1; base += 2 * STEP) {
-        step(b0, b1, base);
-        if (base + STEP >= r1) break;
-        step(b1, b0, base + STEP);
+    if constexpr (V_LDS) {
+        // large K: one register buffer, refilled once the step has read it (with
+        // the amplitudes converted twice, 21 tiles fit two waves per SIMD)
+        TP buf[WPT];
+        fetch(buf, base + row);
+        for (; base < r1; base += STEP) step(buf, buf, base);
+    } else {
+        // two buffers, two steps per trip so that they swap by name
+        TP b0[WPT], b1[WPT];
+        fetch(b0, base + row);
+        for (; base < r1; base += 2 * STEP) {
+            step(b0, b1, base);
+            if (base + STEP >= r1) break;
+            step(b1, b0, base + STEP);
+        }
     }
     if (bad) atomicOr(flag, 1u);
     // tile sums in wave order; item j of lane l is row l / 16 + 4 j, column l % 16
