@@ -156,9 +156,13 @@ __global__ __launch_bounds__(kHThreads) void hess_mfma_kernel(const T *__restric
 #pragma unroll
     for (int i = 0; i < NTL; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
 
-    // amplitudes of event e (zero outside the block's rows or beyond k).  With
-    // rows of at least KP elements every load stays inside its row; otherwise
-    // the element index is clamped.  Either way the loads need no branch.
+    // amplitudes of event e (row index clamped into the sample).  With rows of
+    // at least KP elements every load stays inside its row and takes the row as
+    // it is: a row outside the block's range gets u = 0 when it is formed (the
+    // block whose row it is forms and checks it), and the columns past k meet
+    // V = 0 in z and reach only entries of G past k, which are not read.  With
+    // narrower rows the element index is clamped and the values past k or
+    // outside the range are zeroed.  Either way the loads need no branch.
     const bool wide = ld >= KP;
     auto fetch = [&](TP (&dst)[WPT], int64_t e) {
         const bool ok_e = e < r1;
@@ -166,10 +170,7 @@ __global__ __launch_bounds__(kHThreads) void hess_mfma_kernel(const T *__restric
         if (wide) {
             const TP *q = reinterpret_cast<const TP *>(rp) + sub;
 #pragma unroll
-            for (int w = 0; w < WPT; ++w) {
-                const TP v = q[4 * w];
-                dst[w] = (ok_e && 4 * w + sub < k) ? v : TP{};
-            }
+            for (int w = 0; w < WPT; ++w) dst[w] = q[4 * w];
         } else {
 #pragma unroll
             for (int w = 0; w < WPT; ++w) {
@@ -212,7 +213,11 @@ __global__ __launch_bounds__(kHThreads) void hess_mfma_kernel(const T *__restric
             ui = 0.0;
             if (valid) {
                 if (I > 0.0 && isfinite(I)) {
-                    const double rI = 1.0 / I;          // 1 / z = conj(z) / I
+                    // 1 / z = conj(z) / I; 1 / I from the hardware reciprocal and
+                    // two Newton steps (a few ulp at most)
+                    double rI = __builtin_amdgcn_rcp(I);
+                    rI = fma(rI, fma(-I, rI, 1.0), rI);
+                    rI = fma(rI, fma(-I, rI, 1.0), rI);
                     ur = zr * rI;
                     ui = -zi * rI;
                 } else {
