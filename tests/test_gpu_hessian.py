@@ -85,3 +85,28 @@ def test_hessian_identities_and_edges():
         # no data events, Eq. 2 form: H = 0
         c.set_amplitudes("data", s.A_data[:0])
         assert np.all(c.hessian(V) == 0)
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf])
+def test_hessian_nonfinite_rows(bad):
+    """A non-finite amplitude in one data row gives PWA_E_DOMAIN wherever the row
+    falls (first and last rows, rows that a neighbouring block's last step reads
+    past its range), and the context then gives the unchanged result on clean
+    rows.  1e5 rows spread over more blocks than one step's 64 rows each."""
+    import paper_1108_5882_amd as pwa
+    k, nd = 16, 100000
+    s = synth.make_sample(1, n_data=nd, n_mc=30000, k=k, seed=8)
+    V = synth.eval_vectors(1, 1, k, seed=8)[0]
+    with pwa.Context(0, "f32") as c:
+        c.set_amplitudes("data", s.A_data)
+        c.set_amplitudes("mc", s.A_mc)
+        H0 = c.hessian(V)
+        for row in (0, 97, 98, 100, 50001, nd - 1):
+            _say(f"  non-finite ({bad}) in data row {row}")
+            A = s.A_data.copy()
+            A[row, 3] = complex(bad, 0.0)
+            c.set_amplitudes("data", A)
+            with pytest.raises(pwa.DomainError):
+                c.hessian(V)
+        c.set_amplitudes("data", s.A_data)
+        assert np.array_equal(c.hessian(V), H0)
