@@ -246,44 +246,46 @@ __global__ __launch_bounds__(kHThreads) void hess_mfma_kernel(const T *__restric
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     };
-    // one step: form the step's rows from cur, load the next step's rows into nxt
-    // (in flight during the MFMAs), then the step's MFMAs
-    auto step = [&](const TP (&cur)[WPT], TP (&nxt)[WPT], int64_t b) {
+    // one step: form the step's rows from buf, refill buf with the next step's
+    // rows (in flight during the MFMAs), then the step's MFMAs
+    auto step = [&](TP (&buf)[WPT], int64_t b) {
         const bool valid = b + row < r1;
-        form(0, cur, X, valid);
-        form(1, cur, X, valid);
+        form(0, buf, X, valid);
+        form(1, buf, X, valid);
         slab_fence();                                   // the previous step's reads come first
-        form(2, cur, X, valid);
-        form(3, cur, X, valid);
-        fetch(nxt, b + STEP + row);
+        form(2, buf, X, valid);
+        form(3, buf, X, valid);
+        fetch(buf, b + STEP + row);
         __builtin_amdgcn_sched_barrier(0);              // the loads stay ahead of the MFMAs
         slab_fence();
         const double *xm = X + mofs;
+        if constexpr (NT <= 2) {
+            // few column blocks: every k-step's operands are read before the first MFMA
+            double colv[kHRows / 4][NT];
 #pragma unroll
-        for (int ks = 0; ks < kHRows / 4; ++ks) {
-            double colv[NT];
+            for (int ks = 0; ks < kHRows / 4; ++ks)
 #pragma unroll
-            for (int c = 0; c < NT; ++c) colv[c] = xm[4 * ks * XS + 4 * (ks & 1) + 16 * c];
-            mfma_tiles<NT, T0>(acc, colv, std::make_integer_sequence<int, NTL>{});
+                for (int c = 0; c < NT; ++c) colv[ks][c] = xm[4 * ks * XS + 4 * (ks & 1) + 16 * c];
+            __builtin_amdgcn_sched_barrier(0);          // the reads stay ahead of the MFMAs
+#pragma unroll
+            for (int ks = 0; ks < kHRows / 4; ++ks)
+                mfma_tiles<NT, T0>(acc, colv[ks], std::make_integer_sequence<int, NTL>{});
+        } else {
+#pragma unroll
+            for (int ks = 0; ks < kHRows / 4; ++ks) {
+                double colv[NT];
+#pragma unroll
+                for (int c = 0; c < NT; ++c) colv[c] = xm[4 * ks * XS + 4 * (ks & 1) + 16 * c];
+                mfma_tiles<NT, T0>(acc, colv, std::make_integer_sequence<int, NTL>{});
+            }
         }
     };
+    // one register buffer of rows, refilled once the step has read it (at large
+    // K, with the amplitudes converted twice, 21 tiles fit two waves per SIMD)
     int64_t base = r0 + kHRows * wave;
-    if constexpr (V_LDS) {
-        // large K: one register buffer, refilled once the step has read it (with
-        // the amplitudes converted twice, 21 tiles fit two waves per SIMD)
-        TP buf[WPT];
-        fetch(buf, base + row);
-        for (; base < r1; base += STEP) step(buf, buf, base);
-    } else {
-        // two buffers, two steps per trip so that they swap by name
-        TP b0[WPT], b1[WPT];
-        fetch(b0, base + row);
-        for (; base < r1; base += 2 * STEP) {
-            step(b0, b1, base);
-            if (base + STEP >= r1) break;
-            step(b1, b0, base + STEP);
-        }
-    }
+    TP buf[WPT];
+    fetch(buf, base + row);
+    for (; base < r1; base += STEP) step(buf, base);
     if (bad) atomicOr(flag, 1u);
     // tile sums in wave order; item j of lane l is row l / 16 + 4 j, column l % 16
     double *Gs = lds;
