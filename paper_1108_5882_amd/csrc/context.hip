@@ -74,6 +74,8 @@ struct pwa_ctx {
     unsigned long long *done_dev = nullptr;
     unsigned long long seq = 0;
     uint32_t last_flags = 0;
+    double *h_host = nullptr;        // mapped pinned host memory the Hessian's assembly writes H and its flag to
+    double *h_host_dev = nullptr;    // device address of h_host
 
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -796,6 +798,7 @@ pwa_status pwa_destroy(pwa_ctx *ctx) {
     if (ctx->partials) (void)hipFree(ctx->partials);
     if (ctx->out_dev) (void)hipFree(ctx->out_dev);
     if (ctx->out_host) (void)hipHostFree(ctx->out_host);
+    if (ctx->h_host) (void)hipHostFree(ctx->h_host);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return PWA_OK;
@@ -1000,15 +1003,26 @@ pwa_status pwa_hessian(pwa_ctx *ctx, const double *V, double *H) {
     if (need_mc && (st = ensure_gram(ctx)) != PWA_OK) return st;
     const int blocks = hessian_blocks(ctx->prec, k, ctx->cu_count, nd);
     const size_t n_work = hessian_work_doubles(k, blocks), n_h = 4 * (size_t)k * k + 1;
-    const size_t doubles = n_work + n_h + 1;
+    const size_t doubles = n_work + 1;                  // the work buffer, then the status word
     const size_t cap0 = ctx->h_cap;
     if ((st = grow(ctx, &ctx->h_buf, &ctx->h_cap, sizeof(double) * doubles, "hipMalloc(hessian)"))) return st;
     if (ctx->h_cap != cap0 || ctx->hess_layout[0] != k || ctx->hess_layout[1] != blocks) ctx->hess_clean = false;
     ctx->hess_layout[0] = k;
     ctx->hess_layout[1] = blocks;
+    if (!ctx->h_host) {
+        // H and its status value go straight to mapped host memory (sized for the largest K)
+        hipError_t he = hipHostMalloc(&ctx->h_host, sizeof(double) * (4 * (size_t)PWA_MAX_K * PWA_MAX_K + 1),
+                                      hipHostMallocMapped | hipHostMallocCoherent);
+        if (he == hipSuccess) he = hipHostGetDevicePointer((void **)&ctx->h_host_dev, ctx->h_host, 0);
+        if (he != hipSuccess) {
+            if (ctx->h_host) (void)hipHostFree(ctx->h_host);
+            ctx->h_host = nullptr;
+            ctx->h_host_dev = nullptr;
+            return hip_fail(ctx, he, "hipHostMalloc(hessian output)");
+        }
+    }
     double *work = static_cast<double *>(ctx->h_buf);
-    double *Hd = work + n_work;
-    unsigned *flag = reinterpret_cast<unsigned *>(Hd + n_h);
+    unsigned *flag = reinterpret_cast<unsigned *>(work + n_work);
     // without MC rows (Eq. 2 form, no data) there is no normalisation term
     const double *M = need_mc ? ctx->gram : nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1024,16 +1038,13 @@ pwa_status pwa_hessian(pwa_ctx *ctx, const double *V, double *H) {
     const bool clear = !ctx->hess_clean;
     ctx->hess_clean = false;
     hipError_t e = launch_hessian(ctx->prec, ctx->s[0].A, nd, ctx->ld, k, V, M, (double)nd, ctx->extended, work,
-                                  blocks, clear, flag, Hd, ctx->stream);
+                                  blocks, clear, flag, ctx->h_host_dev, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "hessian launch");
     if (ctx->timing) PWA_HIP(ctx, hipEventRecord(e1, ctx->stream), "hipEventRecord");
-    std::vector<double> h(n_h);
-    PWA_HIP(ctx, hipMemcpyAsync(h.data(), Hd, sizeof(double) * n_h, hipMemcpyDeviceToHost, ctx->stream),
-            "hipMemcpyAsync(H)");
     PWA_HIP(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
     ctx->hess_clean = true;
-    std::copy(h.begin(), h.end() - 1, H);
-    ctx->last_flags = h.back() != 0.0 ? 1u : 0u;
+    std::copy(ctx->h_host, ctx->h_host + (n_h - 1), H);
+    ctx->last_flags = ctx->h_host[n_h - 1] != 0.0 ? 1u : 0u;
     return ctx->last_flags ? fail(ctx, PWA_E_DOMAIN, "zero coherent sum or non-positive normalisation") : PWA_OK;
 }
 
