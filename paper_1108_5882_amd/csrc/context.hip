@@ -81,7 +81,7 @@ struct pwa_ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> batch_events;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> hess_events;
-    bool hess_clean = false;   // the Hessian's status word and counters rest at zero
+    bool hess_clean = false;   // the Hessian's status word rests at zero
     int hess_layout[2] = {0, 0};   // (k, blocks) of the work layout they were zeroed for
     std::vector<hipEvent_t> event_pool;   // timing events kept for reuse
 

@@ -19,7 +19,6 @@
 #include <atomic>
 #include <utility>
 
-#include "block_reduce.hpp"
 #include "internal.hpp"
 
 namespace pwa {
@@ -31,7 +30,6 @@ constexpr int kHThreads = 256;
 constexpr int kHWaves = kHThreads / 64;
 constexpr int kHRows = 16;        // events per wave per step (four k-steps of the 16x16x4 MFMA)
 constexpr int kHMaxTiles = 21;    // accumulator tiles per wave in one launch
-constexpr int kHChunk = 32;       // block partials per first-level sum
 
 // Output tiles: the upper triangle of the NT x NT grid of 16 x 16 tiles of G,
 // numbered row by row.
@@ -307,41 +305,35 @@ __global__ __launch_bounds__(kHThreads) void hess_mfma_kernel(const T *__restric
     for (int idx = tid; idx < NTL * 256; idx += kHThreads) out[idx] = Gs[idx];
 }
 
-// Sum of the block partials in two fixed-order levels within one launch:
-// block (x, y) adds the partials of blocks y * kHChunk .. for its 64 entries
-// in block order into p1[y]; the last of column x's blocks to arrive (arrival
-// counter, which it resets) adds p1[0 ..) in chunk order into G.  p1 crosses
-// blocks, so it is stored and loaded as device-scope atomics, and each block
-// waits for its stores before it announces them.
-__global__ __launch_bounds__(64) void hess_sum_kernel(const double *__restrict__ partials, int nblocks, int entries,
-                                                      double *__restrict__ p1, unsigned *__restrict__ counters,
-                                                      double *__restrict__ Gm) {
-    __shared__ unsigned s_last;
-    const int e = blockIdx.x * 64 + threadIdx.x, c = blockIdx.y, nch = gridDim.y;
+// Sum of the block partials into G in one fixed order: a block of 256 threads
+// takes 16 entries; thread r of an entry (r = 0 .. 15) adds the partials of
+// blocks r, r + 16, ... in block order (32 loads in flight), then the 16 sums
+// of the entry are added in r order.
+constexpr int kHSumSlices = 16;
+__global__ __launch_bounds__(256) void hess_sum_kernel(const double *__restrict__ partials, int nblocks, int entries,
+                                                       double *__restrict__ Gm) {
+    __shared__ double part[kHSumSlices][16];
+    const int tid = threadIdx.x, el = tid & 15, r = tid >> 4;
+    const int e = blockIdx.x * 16 + el;
+    double s = 0.0;
     if (e < entries) {
-        const int b0 = c * kHChunk, b1 = b0 + kHChunk < nblocks ? b0 + kHChunk : nblocks;
-        double sum = 0.0;
-#pragma unroll 8
-        for (int b = b0; b < b1; ++b) sum += partials[(int64_t)b * entries + e];
-        st_dev(p1 + (int64_t)c * entries + e, sum);
-    }
-    wait_stores();
-    __syncthreads();
-    if (threadIdx.x == 0) s_last = atomicAdd(&counters[blockIdx.x], 1u) == (unsigned)(nch - 1);
-    __syncthreads();
-    if (!s_last) return;
-    if (threadIdx.x == 0) __hip_atomic_store(&counters[blockIdx.x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (e < entries) {
-        double sum = 0.0;
-        for (int c0 = 0; c0 < nch; c0 += 16) {
-            double v[16];
+        for (int b0 = r; b0 < nblocks; b0 += 32 * kHSumSlices) {
+            double v[32];
 #pragma unroll
-            for (int u = 0; u < 16; ++u)
-                v[u] = c0 + u < nch ? ld_dev(p1 + (int64_t)(c0 + u) * entries + e) : 0.0;
+            for (int u = 0; u < 32; ++u) {
+                const int b = b0 + u * kHSumSlices;
+                v[u] = b < nblocks ? partials[(int64_t)b * entries + e] : 0.0;
+            }
 #pragma unroll
-            for (int u = 0; u < 16; ++u) sum += v[u];
+            for (int u = 0; u < 32; ++u) s += v[u];
         }
-        Gm[e] = sum;
+    }
+    part[r][el] = s;
+    __syncthreads();
+    if (r == 0 && e < entries) {
+        double t = 0.0;
+        for (int q = 0; q < kHSumSlices; ++q) t += part[q][el];
+        Gm[e] = t;
     }
 }
 
@@ -505,7 +497,6 @@ hipError_t launch_data_pass(const T *A, int64_t n, int64_t ld, int k, const Hess
 
 int hess_kp(int k) { return 8 * ((k + 7) / 8); }
 size_t hess_entries(int k) { return (size_t)tile_count(hess_kp(k) / 8) * 256; }
-int hess_chunks(int blocks) { return (blocks + kHChunk - 1) / kHChunk; }
 
 }  // namespace
 
@@ -524,8 +515,8 @@ int hessian_blocks(pwa_prec prec, int k, int cu_count, int64_t n) {
 }
 
 size_t hessian_work_doubles(int k, int blocks) {
-    const size_t entries = hess_entries(k), cols = (entries + 63) / 64;
-    return (size_t)blocks * entries + (size_t)hess_chunks(blocks) * entries + entries + (cols + 1) / 2;
+    const size_t entries = hess_entries(k);
+    return (size_t)blocks * entries + entries;          // block partials, then G
 }
 
 hipError_t launch_hessian(pwa_prec prec, const void *A, int64_t n, int64_t ld, int k, const double *V,
@@ -534,14 +525,11 @@ hipError_t launch_hessian(pwa_prec prec, const void *A, int64_t n, int64_t ld, i
     if (k < 1 || k > PWA_MAX_K || blocks < 1) return hipErrorInvalidValue;
     HessV hv{};
     for (int i = 0; i < 2 * k; ++i) hv.v[i] = V[i];
-    const int entries = (int)hess_entries(k), cols = (entries + 63) / 64;
+    const int entries = (int)hess_entries(k);
     double *partials = work;
-    double *p1 = partials + (size_t)blocks * entries;
-    double *Gm = p1 + (size_t)hess_chunks(blocks) * entries;
-    unsigned *counters = reinterpret_cast<unsigned *>(Gm + entries);
+    double *Gm = partials + (size_t)blocks * entries;
     hipError_t e;
-    if (clear) {            // the status word and the arrival counters rest at zero between calls
-        if ((e = hipMemsetAsync(counters, 0, sizeof(unsigned) * cols, stream)) != hipSuccess) return e;
+    if (clear) {            // the status word rests at zero between calls
         if ((e = hipMemsetAsync(flag, 0, sizeof(unsigned), stream)) != hipSuccess) return e;
     }
     if (n > 0) {
@@ -550,8 +538,8 @@ hipError_t launch_hessian(pwa_prec prec, const void *A, int64_t n, int64_t ld, i
                 : launch_data_pass(static_cast<const double *>(A), n, ld, k, hv, partials, flag, blocks, stream);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(hess_sum_kernel, dim3(cols, hess_chunks(blocks)), dim3(64), 0, stream, partials,
-                       n > 0 ? blocks : 0, entries, p1, counters, Gm);
+    hipLaunchKernelGGL(hess_sum_kernel, dim3(entries / 16), dim3(256), 0, stream, partials, n > 0 ? blocks : 0,
+                       entries, Gm);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(hess_assemble_kernel, dim3((4 * k * k + 255) / 256), dim3(256), 0, stream, Gm, hess_kp(k), M,
                        hv, k, nd, extended, flag, H);

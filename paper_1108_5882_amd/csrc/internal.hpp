@@ -247,10 +247,10 @@ size_t gram_partial_doubles(int k, int blocks);
 // MC matrix M (k x k complex, FP64, 1/N_gen folded in; null when the
 // likelihood has no normalisation term), nd data events and the likelihood
 // form; writes H (2k x 2k row-major, then one status double: 0 ok, 1 domain
-// failure) to H, device memory or mapped host memory.  blocks: hessian_blocks(prec, k, cu_count, n); work:
-// hessian_work_doubles(k, blocks) doubles; flag: one unsigned.  The status
-// word and the arrival counters in work are left at zero by every call that
-// completes; clear = true zeroes them first (new buffers, or after a call
+// failure) to H, device memory or mapped host memory.  blocks:
+// hessian_blocks(prec, k, cu_count, n); work: hessian_work_doubles(k, blocks)
+// doubles; flag: one unsigned.  The status word is left at zero by every call
+// that completes; clear = true zeroes it first (a new buffer, or after a call
 // that did not complete).
 hipError_t launch_hessian(pwa_prec prec, const void *A, int64_t n, int64_t ld, int k, const double *V,
                           const double *M, double nd, int extended, double *work, int blocks, bool clear,
