@@ -239,7 +239,8 @@ __global__ __launch_bounds__(kHThreads) void hess_mfma_kernel(const T *__restric
         }
     };
     auto slab_fence = [] {
-        // LDS operations of one wave complete in order; the fences keep the compiler's
+        // LDS operations of one wave complete in order; the fences keep the compiler
+        // from moving slab reads and writes across this point
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
