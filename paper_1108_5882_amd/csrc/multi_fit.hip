@@ -96,11 +96,11 @@ __device__ void multi_item(const MultiItem &it, const MultiFit &fit, double *slo
         ld_stage(s0, t);
         for (;;) {
             ld_stage(s1, t + kMW);
-            s0.compute(n, t, g, vr, vi, acc_t, acc_r, acc_i);
+            s0.template compute<true>(n, t, g, vr, vi, acc_t, acc_r, acc_i);
             t += kMW;
             if (t >= it.t1) break;
             ld_stage(s0, t + kMW);
-            s1.compute(n, t, g, vr, vi, acc_t, acc_r, acc_i);
+            s1.template compute<true>(n, t, g, vr, vi, acc_t, acc_r, acc_i);
             t += kMW;
             if (t >= it.t1) break;
         }

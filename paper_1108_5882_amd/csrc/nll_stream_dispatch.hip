@@ -107,7 +107,8 @@ void stream_grid(const StreamCfg &cfg, int64_t budget, int64_t n0, int64_t n1, i
 
 hipError_t launch_stream(pwa_prec prec, const StreamCfg &c, int blocks, const StreamArgs &args,
                          hipStream_t stream) {
-    if (!stream_cfg_available(prec, c) || blocks < 1) return hipErrorInvalidValue;
+    // the kernel takes the row stride from its (L, C): the layout width
+    if (!stream_cfg_available(prec, c) || blocks < 1 || args.ld != (int64_t)c.L * c.C) return hipErrorInvalidValue;
     if (prec == PWA_F32) {
         switch (c.C) {
             case 1: return stream_dispatch_f32_c1(c.L, c.U, blocks, args, stream);

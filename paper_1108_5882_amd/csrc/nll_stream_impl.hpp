@@ -17,9 +17,12 @@
 // [jC, jC+C), so one wave instruction reads 64/L whole rows contiguously.
 // Each lane group takes U rows per stage; the loop keeps two stages in
 // registers so the next stage's loads are in flight while the current one is
-// computed.  Loads are unconditional (row index clamped into the sample) so
-// the compiler can count outstanding loads exactly; rows past the end are
-// masked in the arithmetic.  The partial coherent sums are combined across
+// computed.  While every row of the tiles in flight exists, a stage's loads
+// are a wave-uniform tile address plus per-lane and per-row constant offsets
+// with no masks; the last tiles of each wave load with the row index clamped
+// into the sample (always a valid address, so the loads stay unconditional
+// and the compiler can count them) and mask rows past the end in the
+// arithmetic.  The partial coherent sums are combined across
 // the L lanes with DPP row operations.
 //
 // Precision (the paper's remark in Section 2): FP32 contexts store and stream
@@ -227,16 +230,25 @@ __device__ __forceinline__ void finish(const StreamArgs &p, double log_scale) {
     }
 }
 
+// Keeps the compiler's scheduler from moving instructions across this point:
+// a stage's loads are issued before the previous stage is computed, so two
+// stages are in flight while it runs (left to itself, the scheduler sinks the
+// loads below the arithmetic and waits for every load at the top of the loop).
+__device__ __forceinline__ void fence_sched() { __builtin_amdgcn_sched_barrier(0); }
+
 // One stage: U rows per lane group.
 template <typename T, int L, int C, int U, int SEG>
 struct Stage {
     T a[U][2 * C];
     T w[U];
 
+    static constexpr int G = 64 / L;
+    static constexpr int LD = L * C;   // row stride in complex values: the layout width
+
     // rows t*ROWS + u*G + g, clamped into [0, n): always a valid address
+    // (ld: row stride in complex values)
     __device__ __forceinline__ void load(const T *__restrict__ A, const T *__restrict__ W,
                                          int64_t n, int64_t ld, int64_t tile, int g, int j) {
-        constexpr int G = 64 / L;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             int64_t row = tile * (G * U) + (int64_t)u * G + g;
@@ -246,13 +258,31 @@ struct Stage {
         }
     }
 
+    // A tile whose rows all exist, row stride LD: the tile's base address is
+    // the same in every lane (tile is wave-uniform), each lane adds a fixed
+    // offset, and the rows u*G apart are constant offsets from it, so no
+    // per-row address arithmetic or clamping is needed.  SEG 1 here needs W.
+    __device__ __forceinline__ void load_full(const T *__restrict__ A, const T *__restrict__ W,
+                                              int64_t tile, int g, int j) {
+        if constexpr (SEG == 1) {
+            const T *Wl = W + tile * (int64_t)(G * U) + g;
+#pragma unroll
+            for (int u = 0; u < U; ++u) w[u] = load_nt(Wl + u * G);
+        }
+        const T *At = A + tile * (int64_t)(G * U * LD * 2);
+        const T *Al = At + (g * LD + j * C) * 2;
+#pragma unroll
+        for (int u = 0; u < U; ++u) RowLoad<T, C>::load(Al + u * G * LD * 2, a[u]);
+    }
+
+    // MASK: rows past n exist in the tile (clamped loads) and add nothing.
+    template <bool MASK>
     __device__ __forceinline__ void compute(int64_t n, int64_t tile, int g, const double (&vr)[C],
                                             const double (&vi)[C], double &acc_t,
                                             double (&acc_r)[C], double (&acc_i)[C]) const {
-        constexpr int G = 64 / L;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const bool valid = tile * (G * U) + (int64_t)u * G + g < n;
+            const bool valid = !MASK || tile * (G * U) + (int64_t)u * G + g < n;
             double da[2 * C];
 #pragma unroll
             for (int q = 0; q < 2 * C; ++q) da[q] = (double)a[u][q];
@@ -274,7 +304,7 @@ struct Stage {
                 ur = zr * rI;
                 ui = zi * rI;
             } else {
-                const double wd = valid ? (double)w[u] : 0.0;
+                const double wd = valid ? (SEG == 2 ? 1.0 : (double)w[u]) : 0.0;
                 acc_t = fma(wd, I, acc_t);
                 ur = wd * zr;
                 ui = wd * zi;
@@ -290,29 +320,55 @@ struct Stage {
     }
 };
 
-// Streams one segment.  SEG 0: data (ln I, conj(A) z / I); SEG 1: MC (w I, w conj(A) z).
+// Streams one segment.  SEG 0: data (ln I, conj(A) z / I); SEG 1: MC with
+// weights w (w I, w conj(A) z); SEG 2: MC with unit weights (I, conj(A) z).
+// Whether the MC rows carry weights is a compile-time choice: a run-time test
+// around the weight load would put a branch in the loop, at whose join the
+// compiler waits for every load in flight, the next stage's prefetch included.
 template <typename T, int L, int C, int U, int SEG>
 __device__ __forceinline__ void stream_segment(const T *__restrict__ A, const T *__restrict__ W,
-                                               int64_t n, int64_t ld, int64_t wave0,
+                                               int64_t n, int64_t wave0,
                                                int64_t nwaves, const double (&vr)[C],
                                                const double (&vi)[C], double &acc_t,
                                                double (&acc_r)[C], double (&acc_i)[C]) {
     constexpr int ROWS = (64 / L) * U;
+    constexpr int64_t LD = L * C;
     const int lane = threadIdx.x & 63;
     const int g = lane / L;
     const int j = lane % L;
     const int64_t ntiles = (n + ROWS - 1) / ROWS;
+    const int64_t nfull = n / ROWS;   // tiles whose rows all exist
     int64_t t = wave0;
     if (t >= ntiles) return;
     Stage<T, L, C, U, SEG> s0, s1;
-    s0.load(A, W, n, ld, t, g, j);
+    if (t + 2 * nwaves < nfull) {
+        // every tile loaded here is whole: no clamping, no row masks
+        s0.load_full(A, W, t, g, j);
+        fence_sched();
+        do {
+            s1.load_full(A, W, t + nwaves, g, j);
+            fence_sched();
+            s0.template compute<false>(n, t, g, vr, vi, acc_t, acc_r, acc_i);
+            t += nwaves;
+            s0.load_full(A, W, t + nwaves, g, j);
+            fence_sched();
+            s1.template compute<false>(n, t, g, vr, vi, acc_t, acc_r, acc_i);
+            t += nwaves;
+        } while (t + 2 * nwaves < nfull);
+    } else {
+        s0.load(A, W, n, LD, t, g, j);
+        fence_sched();
+    }
+    // the last tiles of this wave (s0 holds tile t): clamped loads, masked rows
     for (;;) {
-        s1.load(A, W, n, ld, t + nwaves, g, j);
-        s0.compute(n, t, g, vr, vi, acc_t, acc_r, acc_i);
+        s1.load(A, W, n, LD, t + nwaves, g, j);
+        fence_sched();
+        s0.template compute<true>(n, t, g, vr, vi, acc_t, acc_r, acc_i);
         t += nwaves;
         if (t >= ntiles) break;
-        s0.load(A, W, n, ld, t + nwaves, g, j);
-        s1.compute(n, t, g, vr, vi, acc_t, acc_r, acc_i);
+        s0.load(A, W, n, LD, t + nwaves, g, j);
+        fence_sched();
+        s1.template compute<true>(n, t, g, vr, vi, acc_t, acc_r, acc_i);
         t += nwaves;
         if (t >= ntiles) break;
     }
@@ -324,7 +380,7 @@ __global__ __launch_bounds__(NT) void nll_stream_kernel(StreamArgs p) {
     constexpr int SLOT = 2 * C + 1;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wid = tid >> 6;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
     const int j = lane % L;
 
     // V slice of this lane (FP64)
@@ -352,11 +408,14 @@ __global__ __launch_bounds__(NT) void nll_stream_kernel(StreamArgs p) {
     for (int c = 0; c < C; ++c) acc_r[c] = acc_i[c] = 0.0;
 
     if (seg == 0)
-        stream_segment<T, L, C, U, 0>(static_cast<const T *>(p.A[0]), nullptr, p.n[0], p.ld, wave0,
+        stream_segment<T, L, C, U, 0>(static_cast<const T *>(p.A[0]), nullptr, p.n[0], wave0,
                                       nwaves, vr, vi, acc_t, acc_r, acc_i);
-    else
+    else if (p.w)
         stream_segment<T, L, C, U, 1>(static_cast<const T *>(p.A[1]), static_cast<const T *>(p.w),
-                                      p.n[1], p.ld, wave0, nwaves, vr, vi, acc_t, acc_r, acc_i);
+                                      p.n[1], wave0, nwaves, vr, vi, acc_t, acc_r, acc_i);
+    else
+        stream_segment<T, L, C, U, 2>(static_cast<const T *>(p.A[1]), nullptr, p.n[1], wave0,
+                                      nwaves, vr, vi, acc_t, acc_r, acc_i);
 
     // lanes with the same j across the wave's row groups
 #pragma unroll
