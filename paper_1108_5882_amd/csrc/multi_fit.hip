@@ -40,35 +40,37 @@ __device__ __forceinline__ int wave_of(int j, int c) {
     else return j * C + c;
 }
 
-// Row loads of the chunked layout (same registers as Stage::load fills).
-template <int L, int C, int U, int SEG>
+// Row loads of the chunked layout (same registers as Stage::load fills), row
+// stride L * C complex.  FULL: every row of the tile exists (wave-uniform tile
+// base, constant offsets, no clamping; SEG 1 then needs W); otherwise rows
+// are clamped into [0, n).
+template <int L, int C, int U, int SEG, bool FULL>
 __device__ __forceinline__ void load_chunked(Stage<float, L, C, U, SEG> &st, const float *__restrict__ A,
-                                             const float *__restrict__ W, int64_t n, int64_t ld, int64_t tile,
+                                             const float *__restrict__ W, int64_t n, int64_t tile,
                                              int g, int j) {
     typedef float f4c __attribute__((ext_vector_type(4)));
     typedef const f4c __attribute__((address_space(1))) *gp4;
+    typedef const float __attribute__((address_space(1))) *gpf;
     constexpr int G = 64 / L;
+    constexpr int64_t LD = L * C;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         int64_t row = tile * (G * U) + (int64_t)u * G + g;
-        row = row < n ? row : n - 1;
+        if constexpr (!FULL) row = row < n ? row : n - 1;
+        if constexpr (SEG == 1) st.w[u] = FULL || W ? __builtin_nontemporal_load((gpf)(W + row)) : 1.f;
 #pragma unroll
         for (int i = 0; i < C / 2; ++i) {
-            const f4c v = __builtin_nontemporal_load((gp4)(A + 2 * (row * ld + 2 * (j + L * i))));
+            const f4c v = __builtin_nontemporal_load((gp4)(A + 2 * (row * LD + 2 * (j + L * i))));
             st.a[u][4 * i + 0] = v.x;
             st.a[u][4 * i + 1] = v.y;
             st.a[u][4 * i + 2] = v.z;
             st.a[u][4 * i + 3] = v.w;
         }
-        if constexpr (SEG == 1) {
-            typedef const float __attribute__((address_space(1))) *gpf;
-            st.w[u] = W ? __builtin_nontemporal_load((gpf)(W + row)) : 1.f;
-        }
     }
 }
 
 template <int L, int C, int U, int SEG, bool CH = false>
-__device__ void multi_item(const MultiItem &it, const MultiFit &fit, double *slot, double *red) {
+__device__ __forceinline__ void multi_item(const MultiItem &it, const MultiFit &fit, double *slot, double *red) {
     constexpr int SLOT = 2 * C + 1;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int g = lane / L, j = lane % L;
@@ -83,26 +85,53 @@ __device__ void multi_item(const MultiItem &it, const MultiFit &fit, double *slo
         vr[c] = a < fit.k ? V[2 * a] : 0.0;
         vi[c] = a < fit.k ? V[2 * a + 1] : 0.0;
     }
+    // row stride L * C (the item's width selected this shape)
     auto ld_stage = [&](Stage<float, L, C, U, SEG> &st, int64_t tt) {
-        if constexpr (CH) load_chunked<L, C, U, SEG>(st, A, W, n, fit.ld, tt, g, j);
-        else st.load(A, W, n, fit.ld, tt, g, j);
+        if constexpr (CH) load_chunked<L, C, U, SEG, false>(st, A, W, n, tt, g, j);
+        else st.load(A, W, n, (int64_t)(L * C), tt, g, j);
+    };
+    auto ld_full = [&](Stage<float, L, C, U, SEG> &st, int64_t tt) {
+        if constexpr (CH) load_chunked<L, C, U, SEG, true>(st, A, W, n, tt, g, j);
+        else st.load_full(A, W, tt, g, j);
     };
     double acc_t = 0.0, acc_r[C], acc_i[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc_r[c] = acc_i[c] = 0.0;
+    constexpr int ROWS = (64 / L) * U;
+    const int64_t nfull = n / ROWS;   // tiles whose rows all exist
     int64_t t = it.t0 + wid;
     if (t < it.t1) {
         Stage<float, L, C, U, SEG> s0, s1;
-        ld_stage(s0, t);
-        for (;;) {
+        // the same two-stage schedule as the single-fit pass: whole tiles
+        // without clamping or masks while they last, then the clamped loads
+        if (t + kMW < it.t1 && t + 2 * kMW < nfull) {
+            ld_full(s0, t);
+            stream_detail::fence_sched();
+            do {
+                ld_full(s1, t + kMW);
+                stream_detail::fence_sched();
+                s0.template compute<false>(n, t, g, vr, vi, acc_t, acc_r, acc_i);
+                t += kMW;
+                ld_full(s0, t + kMW);
+                stream_detail::fence_sched();
+                s1.template compute<false>(n, t, g, vr, vi, acc_t, acc_r, acc_i);
+                t += kMW;
+            } while (t + kMW < it.t1 && t + 2 * kMW < nfull);
+        } else {
+            ld_stage(s0, t);
+            stream_detail::fence_sched();
+        }
+        // s0 holds tile t
+        while (t < it.t1) {
             ld_stage(s1, t + kMW);
+            stream_detail::fence_sched();
             s0.template compute<true>(n, t, g, vr, vi, acc_t, acc_r, acc_i);
             t += kMW;
             if (t >= it.t1) break;
             ld_stage(s0, t + kMW);
+            stream_detail::fence_sched();
             s1.template compute<true>(n, t, g, vr, vi, acc_t, acc_r, acc_i);
             t += kMW;
-            if (t >= it.t1) break;
         }
     }
 #pragma unroll
@@ -148,7 +177,7 @@ __device__ void multi_item(const MultiItem &it, const MultiFit &fit, double *slo
 }
 
 template <int SEG>
-__device__ void dispatch_item(const MultiItem &it, const MultiFit &fit, double *slot, double *red) {
+__device__ __forceinline__ void dispatch_item(const MultiItem &it, const MultiFit &fit, double *slot, double *red) {
     switch (fit.ld) {
         case 4: multi_item<2, 2, 4, SEG>(it, fit, slot, red); break;
         case 6: multi_item<2, 3, 2, SEG>(it, fit, slot, red); break;
@@ -174,10 +203,14 @@ __global__ __launch_bounds__(kMT) void multi_stream_kernel(MultiArgs p) {
         const MultiItem it = p.items[item];
         const MultiFit fit = p.fits[it.fit];
         double *slot = p.partials + (int64_t)item * kMultiSlot;
+        // MC rows with weights (segment kind 1) or unit weights (2): a
+        // compile-time choice, so the row loop holds no branch on it
         if (it.seg == 0)
             dispatch_item<0>(it, fit, slot, red);
-        else
+        else if (fit.w_mc)
             dispatch_item<1>(it, fit, slot, red);
+        else
+            dispatch_item<2>(it, fit, slot, red);
     }
 }
 
