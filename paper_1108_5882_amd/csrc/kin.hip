@@ -108,9 +108,12 @@ __global__ __launch_bounds__(kKinThreads) void kin_kernel(KinArgs p) {
 
     // per-lane wave constants (padded waves: V = 0 and a harmless lineshape):
     // V, m_a, m_a Gamma_a, the derivative factors -4 m_a, -2 m_a, -2 Gamma_a,
-    // the Y_J^0 normalisation and the spin
-    double vr[kKinW], vi[kKinW], ma[kKinW], mg[kKinW], c4m[kKinW], c2m[kKinW], c2g[kKinW], yn[kKinW];
-    int sp[kKinW];
+    // and Y_J^0 as a polynomial in x = cos theta, yc[q][i] the coefficient of
+    // x^i (the normalisation folded in), so that every wave evaluates it with
+    // the same four FMAs whatever its spin (a per-wave choice among the
+    // Legendre polynomials would branch on the lane's spin)
+    double vr[kKinW], vi[kKinW], ma[kKinW], mg[kKinW], c4m[kKinW], c2m[kKinW], c2g[kKinW];
+    double yc[kKinW][5];
 #pragma unroll
     for (int q = 0; q < kKinW; ++q) {
         const int a = j * kKinW + q;
@@ -125,8 +128,14 @@ __global__ __launch_bounds__(kKinThreads) void kin_kernel(KinArgs p) {
         c4m[q] = -4.0 * ma[q];
         c2m[q] = -2.0 * ma[q];
         c2g[q] = -2.0 * ga;
-        sp[q] = live ? p.spin[a] : 0;
-        yn[q] = live ? sqrt((2.0 * sp[q] + 1.0) * 0.079577471545947667884) : 0.0;   // 1 / (4 pi)
+        const int J = live ? p.spin[a] : 0;
+        const double yn = live ? sqrt((2.0 * J + 1.0) * 0.079577471545947667884) : 0.0;   // 1 / (4 pi)
+        // P_0 = 1, P_1 = x, P_2 = (3x^2 - 1)/2, P_3 = (5x^3 - 3x)/2, P_4 = (35x^4 - 30x^2 + 3)/8
+        yc[q][0] = yn * (J == 0 ? 1.0 : J == 2 ? -0.5 : J == 4 ? 0.375 : 0.0);
+        yc[q][1] = yn * (J == 1 ? 1.0 : J == 3 ? -1.5 : 0.0);
+        yc[q][2] = yn * (J == 2 ? 1.5 : J == 4 ? -3.75 : 0.0);
+        yc[q][3] = yn * (J == 3 ? 2.5 : 0.0);
+        yc[q][4] = yn * (J == 4 ? 4.375 : 0.0);
     }
 
     const int seg = (int)blockIdx.x < p.nb[0] ? 0 : 1;
@@ -145,17 +154,31 @@ __global__ __launch_bounds__(kKinThreads) void kin_kernel(KinArgs p) {
 #pragma unroll
     for (int q = 0; q < kKinW; ++q) gvr[q] = gvi[q] = gm[q] = gg[q] = 0.0;
 
-    for (int64_t t = (int64_t)bseg * NW + wid; t < ntiles; t += stride) {
+    // each step's (m, cos theta) and weight are loaded one step ahead (row
+    // index clamped into the sample: always a valid address); the weight load
+    // reads the events themselves when there are no weights, so the loop holds
+    // no branch on it
+    const bool has_w = seg && W;
+    const float *Wl = has_w ? W : reinterpret_cast<const float *>(mx);
+    int64_t t = (int64_t)bseg * NW + wid;
+    float2 kin_n = {0.f, 0.f};
+    float w_n = 1.f;
+    if (t < ntiles) {
+        const int64_t e0 = min(t * G + g, n - 1);
+        kin_n = mx[e0];
+        w_n = Wl[e0];
+    }
+    for (; t < ntiles; t += stride) {
         const int64_t e = t * G + g;
         const bool valid = e < n;
-        const int64_t ec = valid ? e : n - 1;
-        const float2 kin = mx[ec];
-        const float wf = (seg && W) ? W[ec] : 1.0f;
+        const float2 kin = kin_n;
+        const float wf = has_w ? w_n : 1.0f;
+        {
+            const int64_t en = min((t + stride) * G + g, n - 1);
+            kin_n = mx[en];
+            w_n = Wl[en];
+        }
         const double m = kin.x, x = kin.y;
-        // Legendre polynomials P_0 .. P_4 (Bonnet's recurrence)
-        const double p1 = x, p2 = 1.5 * x * x - 0.5;
-        const double p3 = (5.0 * x * p2 - 2.0 * p1) * (1.0 / 3.0);
-        const double p4 = (7.0 * x * p3 - 3.0 * p2) * 0.25;
         double bre[kKinW], bim[kKinW], y[kKinW], vbr[kKinW], vbi[kKinW];
         double zr = 0.0, zi = 0.0;
 #pragma unroll
@@ -165,9 +188,7 @@ __global__ __launch_bounds__(kKinThreads) void kin_kernel(KinArgs p) {
             const double r = recip(fma(dre, dre, mg[q] * mg[q]));
             bre[q] = dre * r;
             bim[q] = mg[q] * r;
-            const int J = sp[q];
-            const double pj = J == 0 ? 1.0 : J == 1 ? p1 : J == 2 ? p2 : J == 3 ? p3 : p4;
-            y[q] = yn[q] * pj;
+            y[q] = fma(fma(fma(fma(yc[q][4], x, yc[q][3]), x, yc[q][2]), x, yc[q][1]), x, yc[q][0]);
             // V_a BW_a, then its share of z = sum_a (V_a BW_a) Y_a
             vbr[q] = fma(vr[q], bre[q], -vi[q] * bim[q]);
             vbi[q] = fma(vr[q], bim[q], vi[q] * bre[q]);

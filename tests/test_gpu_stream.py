@@ -319,3 +319,25 @@ def test_autotune_keeps_parity(pwa):
         nll, grad = c.nll_grad(V)
     e_n, e_g = errors(reference(s.A_data, s.A_mc, V), nll, grad)
     assert e_n < 1e-6 and e_g < 1e-6
+
+
+@pytest.mark.parametrize("prec,k,weighted", [("f32", 16, False), ("f32", 16, True), ("f32", 5, True),
+                                             ("f64", 16, False), ("f64", 12, True)])
+def test_whole_tile_loop(pwa, prec, k, weighted):
+    """Samples long enough that every wave streams many tiles on a small grid: the
+    loop over whole tiles (unclamped loads, no row masks) hands over to the
+    clamped, masked loop for the last tiles at several alignments of the row
+    counts (ragged, a multiple of every tile height, one row past one)."""
+    for nd, nm in ((200003, 300017), (196608, 393216), (131073, 262143)):
+        Ad, Am, V, w = _case(7000 + k + nd % 97, nd, nm, k, prec, weighted)
+        ref = reference(Ad, Am, V, w=w)
+        with _ctx(pwa, prec) as c:
+            c.set_amplitudes("data", Ad)
+            c.set_amplitudes("mc", Am, w=w)
+            for (L, C, U) in _configs(c):
+                for bpc in (1, 2):
+                    _say(f"case whole-tile prec={prec} k={k} w={weighted} nd={nd} nm={nm} L={L} C={C} U={U} bpc={bpc}")
+                    c.set_stream_cfg(L, C, U, bpc)
+                    nll, grad = c.nll_grad(V)
+                    e_n, e_g = errors(ref, nll, grad)
+                    assert e_n < TOL[prec] and e_g < TOL[prec], (nd, nm, L, C, U, bpc, e_n, e_g)
