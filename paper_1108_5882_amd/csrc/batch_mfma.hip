@@ -181,7 +181,10 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
             float ts = 0.f;
             // the flag masks of (g, slot): with one k-step (KS = 1) lane `slot` gathers
             // them for one store per group; with more, registers are short (the
-            // gather costs spills) and lane 0 stores each mask
+            // gather costs spills) and every lane stores each (wave-uniform) mask to
+            // its word, one store instruction with no branch around it (a store by
+            // lane 0 alone put an exec-mask branch per slot into the epilogue, whose
+            // blocks the scheduler cannot interleave matrix products across)
             unsigned fw_lo = 0u, fw_hi = 0u;
 #pragma unroll
             for (int rt = 0; rt < 2; ++rt)
@@ -199,7 +202,7 @@ __device__ __forceinline__ void batch_block(const BatchArgs &p, BatchSmem<KS, CT
                             if constexpr (KS == 1) {
                                 fw_lo = writelane_u32((unsigned)mask, slot, fw_lo);
                                 fw_hi = writelane_u32((unsigned)(mask >> 32), slot, fw_hi);
-                            } else if (lane == 0) {
+                            } else {
                                 p.flags[((int64_t)vg * ntiles + t) * (8 * (CT / 2)) + 8 * g + slot] = mask;
                             }
                         }
@@ -607,13 +610,17 @@ __device__ __forceinline__ WeightSplit split_weight(double x) {
 //   sum_j w_j I_j(V) = sum_j w_j I_j(V~) + 2 Re sum_a dV_a conj(H_a),
 // with G_a = sum_i conj(A_ia) z_i / I_i and H_a = sum_j w_j conj(A_ja) z_j
 // (the second-order terms are about 2^-44 of the sums).
-// The block partials of a segment are summed by G = 256 / pstride thread
-// groups (group g takes blocks g, g + G, ...; threads of a group take the
-// pstride values of a block, so each block's partial row is read contiguously),
-// then the G group sums are added in group order: the order is fixed.
-__global__ __launch_bounds__(256) void nll_batch_combine_kernel(BatchArgs p) {
+// The block partials of a segment are summed by G = kCombineThreads / pstride
+// thread groups (group g takes blocks g, g + G, ...; threads of a group take
+// the pstride values of a block, so each block's partial row is read
+// contiguously; eight loads in flight per thread), then the G group sums are
+// added in group order: the order is fixed.  One block per vector reads a few
+// MB of partials, so the block is large to keep many loads in flight.
+constexpr int kCombineThreads = 1024;
+
+__global__ __launch_bounds__(kCombineThreads) void nll_batch_combine_kernel(BatchArgs p) {
     __shared__ double tot[2][1 + 2 * PWA_MAX_K];
-    __shared__ double grp[256];
+    __shared__ double grp[kCombineThreads];
     __shared__ double mv[2 * PWA_MAX_K];
     __shared__ double dv[2 * PWA_MAX_K];
     __shared__ double s_c;
@@ -622,12 +629,12 @@ __global__ __launch_bounds__(256) void nll_batch_combine_kernel(BatchArgs p) {
     const int nblk = p.nb[0] + p.nb[1];
     const int k = p.k;
     const double *base = p.partials + (int64_t)v * nblk * pst;
-    const int G = 256 / pst, g = tid / pst, cc = tid % pst;
+    const int G = kCombineThreads / pst, g = tid / pst, cc = tid % pst;
     for (int sg = 0; sg < 2; ++sg) {
         const int b0 = sg ? p.nb[0] : 0, b1 = sg ? nblk : p.nb[0];
         if (g < G) {
             double s = 0.0;
-#pragma unroll 4
+#pragma unroll 8
             for (int b = b0 + g; b < b1; b += G) s += base[(int64_t)b * pst + cc];
             grp[tid] = s;
         }
@@ -641,13 +648,13 @@ __global__ __launch_bounds__(256) void nll_batch_combine_kernel(BatchArgs p) {
     }
     const double tv = p.vscale[v];
     const double *V = p.V + (int64_t)v * p.vstride;
-    for (int i = tid; i < 2 * k; i += 256) {
+    for (int i = tid; i < 2 * k; i += kCombineThreads) {
         const double sr = (double)p.ascale[i];
         const WeightSplit ws = split_weight(V[i] * tv / sr);
         dv[i] = V[i] - ((double)ws.hi + (double)ws.lo) * sr / tv;
     }
     if (p.gram) {
-        for (int a = tid; a < k; a += 256) {
+        for (int a = tid; a < k; a += kCombineThreads) {
             double r = 0.0, i = 0.0;
             for (int b = 0; b < k; ++b) {
                 const double mr = p.gram[2 * (a * k + b)], mi = p.gram[2 * (a * k + b) + 1];
@@ -702,7 +709,7 @@ __global__ __launch_bounds__(256) void nll_batch_combine_kernel(BatchArgs p) {
     const double c = s_c;
     const bool zero = !p.extended && p.nd_total == 0.0;
     // data sums carry u = t_v Z'/I' (x t_v); MC sums carry w Z' = t_v w z (/ t_v)
-    for (int i = tid; i < 2 * k; i += 256) {
+    for (int i = tid; i < 2 * k; i += kCombineThreads) {
         const double g = tot[0][1 + i] * tv;
         const double h = p.gram ? mv[i] : tot[1][1 + i] / tv;
         out[1 + i] = zero ? 0.0 : 2.0 * (-g + c * h);
@@ -901,7 +908,7 @@ hipError_t launch_rownorm(const float *A, int64_t n, int64_t ld, int k, float *o
 }
 
 hipError_t launch_batch_combine(const BatchArgs &args, hipStream_t stream) {
-    hipLaunchKernelGGL(nll_batch_combine_kernel, dim3(args.nv), dim3(256), 0, stream, args);
+    hipLaunchKernelGGL(nll_batch_combine_kernel, dim3(args.nv), dim3(kCombineThreads), 0, stream, args);
     return hipGetLastError();
 }
 
