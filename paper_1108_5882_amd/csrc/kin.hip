@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kKinThreads) void kin_kernel(KinArgs p) {
     // x^i (the normalisation folded in), so that every wave evaluates it with
     // the same four FMAs whatever its spin (a per-wave choice among the
     // Legendre polynomials would branch on the lane's spin)
-    double vr[kKinW], vi[kKinW], ma[kKinW], mg[kKinW], c4m[kKinW], c2m[kKinW], c2g[kKinW];
+    double vr[kKinW], vi[kKinW], ma[kKinW], ga[kKinW], mg[kKinW];
     double yc[kKinW][5];
 #pragma unroll
     for (int q = 0; q < kKinW; ++q) {
@@ -123,11 +123,8 @@ __global__ __launch_bounds__(kKinThreads) void kin_kernel(KinArgs p) {
         vr[q] = live ? V[2 * a] : 0.0;
         vi[q] = live ? V[2 * a + 1] : 0.0;
         ma[q] = live ? R[2 * a] : 1.0;
-        const double ga = live ? R[2 * a + 1] : 1.0;
-        mg[q] = ma[q] * ga;
-        c4m[q] = -4.0 * ma[q];
-        c2m[q] = -2.0 * ma[q];
-        c2g[q] = -2.0 * ga;
+        ga[q] = live ? R[2 * a + 1] : 1.0;
+        mg[q] = ma[q] * ga[q];
         const int J = live ? p.spin[a] : 0;
         const double yn = live ? sqrt((2.0 * J + 1.0) * 0.079577471545947667884) : 0.0;   // 1 / (4 pi)
         // P_0 = 1, P_1 = x, P_2 = (3x^2 - 1)/2, P_3 = (5x^3 - 3x)/2, P_4 = (35x^4 - 30x^2 + 3)/8
@@ -150,6 +147,8 @@ __global__ __launch_bounds__(kKinThreads) void kin_kernel(KinArgs p) {
     // (one logarithm per 32 events instead of one per event); MC: sum w I
     double acc_t = 0.0, pm = 1.0;
     int pe = 0, cnt = 0;
+    // gm, gg: per wave the sums of Re e and Im e; the constant factors of
+    // dI/dm_a and dI/dGamma_a are applied once after the loop
     double gvr[kKinW], gvi[kKinW], gm[kKinW], gg[kKinW];
 #pragma unroll
     for (int q = 0; q < kKinW; ++q) gvr[q] = gvi[q] = gm[q] = gg[q] = 0.0;
@@ -224,9 +223,8 @@ __global__ __launch_bounds__(kKinThreads) void kin_kernel(KinArgs p) {
             // e = conj(u) V_a Y_a BW_a^2 = (V_a BW_a) conj(g)
             const double er = fma(vbr[q], gr_, vbi[q] * gi_);
             const double ei = fma(vbi[q], gr_, -vbr[q] * gi_);
-            // 2 Re(e (-(2 m_a - i Gamma_a))) and 2 Re(e (i m_a))
-            gm[q] = fma(c4m[q], er, fma(c2g[q], ei, gm[q]));
-            gg[q] = fma(c2m[q], ei, gg[q]);
+            gm[q] += er;
+            gg[q] += ei;
         }
     }
     if (seg == 0) acc_t += log(pm) + (double)pe * 0.69314718055994530942;
@@ -242,6 +240,13 @@ __global__ __launch_bounds__(kKinThreads) void kin_kernel(KinArgs p) {
             gm[q] += __shfl_xor(gm[q], off);
             gg[q] += __shfl_xor(gg[q], off);
         }
+    }
+    // 2 Re(e (-(2 m_a - i Gamma_a))) = -4 m_a Re e - 2 Gamma_a Im e;  2 Re(e (i m_a)) = -2 m_a Im e
+#pragma unroll
+    for (int q = 0; q < kKinW; ++q) {
+        const double sr = gm[q], si = gg[q];
+        gm[q] = fma(-4.0 * ma[q], sr, -2.0 * ga[q] * si);
+        gg[q] = -2.0 * ma[q] * si;
     }
     __shared__ double red[NW][L][1 + 4 * kKinW];
     if (lane < L) {
