@@ -107,12 +107,12 @@ __global__ __launch_bounds__(kKinThreads) void kin_kernel(KinArgs p) {
     const int j = lane % L, g = lane / L;
 
     // per-lane wave constants (padded waves: V = 0 and a harmless lineshape):
-    // V, m_a, m_a Gamma_a, the derivative factors -4 m_a, -2 m_a, -2 Gamma_a,
-    // and Y_J^0 as a polynomial in x = cos theta, yc[q][i] the coefficient of
-    // x^i (the normalisation folded in), so that every wave evaluates it with
-    // the same four FMAs whatever its spin (a per-wave choice among the
-    // Legendre polynomials would branch on the lane's spin)
-    double vr[kKinW], vi[kKinW], ma[kKinW], ga[kKinW], mg[kKinW];
+    // V, m_a^2, m_a Gamma_a and its square, and Y_J^0 as a polynomial in
+    // x = cos theta, yc[q][i] the coefficient of x^i (the normalisation folded
+    // in), so that every wave evaluates it with the same four FMAs whatever its
+    // spin (a per-wave choice among the Legendre polynomials would branch on
+    // the lane's spin)
+    double vr[kKinW], vi[kKinW], ma[kKinW], ga[kKinW], ma2[kKinW], mg[kKinW], mg2[kKinW];
     double yc[kKinW][5];
 #pragma unroll
     for (int q = 0; q < kKinW; ++q) {
@@ -124,7 +124,9 @@ __global__ __launch_bounds__(kKinThreads) void kin_kernel(KinArgs p) {
         vi[q] = live ? V[2 * a + 1] : 0.0;
         ma[q] = live ? R[2 * a] : 1.0;
         ga[q] = live ? R[2 * a + 1] : 1.0;
+        ma2[q] = ma[q] * ma[q];
         mg[q] = ma[q] * ga[q];
+        mg2[q] = mg[q] * mg[q];
         const int J = live ? p.spin[a] : 0;
         const double yn = live ? sqrt((2.0 * J + 1.0) * 0.079577471545947667884) : 0.0;   // 1 / (4 pi)
         // P_0 = 1, P_1 = x, P_2 = (3x^2 - 1)/2, P_3 = (5x^3 - 3x)/2, P_4 = (35x^4 - 30x^2 + 3)/8
@@ -147,8 +149,10 @@ __global__ __launch_bounds__(kKinThreads) void kin_kernel(KinArgs p) {
     // (one logarithm per 32 events instead of one per event); MC: sum w I
     double acc_t = 0.0, pm = 1.0;
     int pe = 0, cnt = 0;
-    // gm, gg: per wave the sums of Re e and Im e; the constant factors of
-    // dI/dm_a and dI/dGamma_a are applied once after the loop
+    // gvr, gvi: per wave the sums of g = conj(A_a) u (u = c z); gm, gg: the sums
+    // of BW_a conj(g).  The mass and width terms need e = (V_a BW_a) conj(g):
+    // V_a and the constant factors of dI/dm_a and dI/dGamma_a are applied to
+    // the sums once after the loop
     double gvr[kKinW], gvi[kKinW], gm[kKinW], gg[kKinW];
 #pragma unroll
     for (int q = 0; q < kKinW; ++q) gvr[q] = gvi[q] = gm[q] = gg[q] = 0.0;
@@ -177,22 +181,26 @@ __global__ __launch_bounds__(kKinThreads) void kin_kernel(KinArgs p) {
             kin_n = mx[en];
             w_n = Wl[en];
         }
-        const double m = kin.x, x = kin.y;
-        double bre[kKinW], bim[kKinW], y[kKinW], vbr[kKinW], vbi[kKinW];
+        const double x = kin.y;
+        // m^2 of an FP32 mass is exact in FP64 (24-bit mantissa squared)
+        const double m2 = (double)kin.x * (double)kin.x;
+        double bre[kKinW], bim[kKinW], ar[kKinW], ai[kKinW];
         double zr = 0.0, zi = 0.0;
 #pragma unroll
         for (int q = 0; q < kKinW; ++q) {
             // BW = 1 / (dre - i mg) = (dre + i mg) / (dre^2 + mg^2), dre = m_a^2 - m^2
-            const double dre = (ma[q] - m) * (ma[q] + m);
-            const double r = recip(fma(dre, dre, mg[q] * mg[q]));
+            const double dre = ma2[q] - m2;
+            const double r = recip(fma(dre, dre, mg2[q]));
             bre[q] = dre * r;
             bim[q] = mg[q] * r;
-            y[q] = fma(fma(fma(fma(yc[q][4], x, yc[q][3]), x, yc[q][2]), x, yc[q][1]), x, yc[q][0]);
-            // V_a BW_a, then its share of z = sum_a (V_a BW_a) Y_a
-            vbr[q] = fma(vr[q], bre[q], -vi[q] * bim[q]);
-            vbi[q] = fma(vr[q], bim[q], vi[q] * bre[q]);
-            zr = fma(vbr[q], y[q], zr);
-            zi = fma(vbi[q], y[q], zi);
+            const double y = fma(fma(fma(fma(yc[q][4], x, yc[q][3]), x, yc[q][2]), x, yc[q][1]), x, yc[q][0]);
+            // A_a = BW_a Y_a, then its share of z = sum_a V_a A_a
+            ar[q] = bre[q] * y;
+            ai[q] = bim[q] * y;
+            zr = fma(vr[q], ar[q], zr);
+            zr = fma(-vi[q], ai[q], zr);
+            zi = fma(vr[q], ai[q], zi);
+            zi = fma(vi[q], ar[q], zi);
         }
         zr = lane_group_sum<L>(zr);
         zi = lane_group_sum<L>(zi);
@@ -215,16 +223,16 @@ __global__ __launch_bounds__(kKinThreads) void kin_kernel(KinArgs p) {
         const double ur = ce * zr, ui = ce * zi;
 #pragma unroll
         for (int q = 0; q < kKinW; ++q) {
-            // g = conj(A_a) u = Y_a conj(BW_a) u  (the V-gradient term)
-            const double gr_ = fma(bre[q], ur, bim[q] * ui) * y[q];
-            const double gi_ = fma(bre[q], ui, -bim[q] * ur) * y[q];
+            // g = conj(A_a) u  (the V-gradient term)
+            const double gr_ = fma(ar[q], ur, ai[q] * ui);
+            const double gi_ = fma(ar[q], ui, -ai[q] * ur);
             gvr[q] += gr_;
             gvi[q] += gi_;
-            // e = conj(u) V_a Y_a BW_a^2 = (V_a BW_a) conj(g)
-            const double er = fma(vbr[q], gr_, vbi[q] * gi_);
-            const double ei = fma(vbi[q], gr_, -vbr[q] * gi_);
-            gm[q] += er;
-            gg[q] += ei;
+            // BW_a conj(g) = conj(u) Y_a BW_a^2; times V_a after the loop it is e
+            gm[q] = fma(bre[q], gr_, gm[q]);
+            gm[q] = fma(bim[q], gi_, gm[q]);
+            gg[q] = fma(bim[q], gr_, gg[q]);
+            gg[q] = fma(-bre[q], gi_, gg[q]);
         }
     }
     if (seg == 0) acc_t += log(pm) + (double)pe * 0.69314718055994530942;
@@ -241,10 +249,12 @@ __global__ __launch_bounds__(kKinThreads) void kin_kernel(KinArgs p) {
             gg[q] += __shfl_xor(gg[q], off);
         }
     }
+    // e = V_a (sum of BW_a conj(g)); then
     // 2 Re(e (-(2 m_a - i Gamma_a))) = -4 m_a Re e - 2 Gamma_a Im e;  2 Re(e (i m_a)) = -2 m_a Im e
 #pragma unroll
     for (int q = 0; q < kKinW; ++q) {
-        const double sr = gm[q], si = gg[q];
+        const double sr = fma(vr[q], gm[q], -vi[q] * gg[q]);
+        const double si = fma(vr[q], gg[q], vi[q] * gm[q]);
         gm[q] = fma(-4.0 * ma[q], sr, -2.0 * ga[q] * si);
         gg[q] = -2.0 * ma[q] * si;
     }
