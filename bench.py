@@ -33,7 +33,9 @@ METRIC = "NLL+grad event-evals/s, batched vs single-V at 1e-6 rel err; %HBM / %M
 HBM_PEAK_GBS = 8000.0
 # committed counter summaries of the single-V kernel, one per launch configuration
 TRAFFIC_GLOB = os.path.join(ROOT, "profiles", "traffic_nll_stream_k16*.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1108_5882_amd", "csrc", "nll_stream_impl.hpp")
+# the files the streaming kernel's code comes from: its loop, and the in-launch
+# combine of the block partials
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1108_5882_amd", "csrc", f) for f in ("nll_stream_impl.hpp", "block_reduce.hpp")]
 
 
 def log(msg):
@@ -41,8 +43,12 @@ def log(msg):
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """SHA-256 prefix of the kernel's source files, concatenated in order."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def stored_traffic(units_per_launch, kernel: str):

@@ -3,7 +3,9 @@
 // last block to arrive in each group (arrival counter) adds the group's
 // partials in block order, and the last group to arrive adds the group sums
 // in group order.  Every addition has a fixed place in that order, so results
-// are bitwise reproducible for a launch configuration.
+// are bitwise reproducible for a launch configuration.  Both levels are
+// compensated (Neumaier) sums, each folding its running error term into its
+// result.
 #pragma once
 
 #include "internal.hpp"
@@ -28,6 +30,14 @@ __device__ __forceinline__ double ld_dev(const double *p) {
 __device__ __forceinline__ void st_sys(double *p, double v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
+// s + x with the rounding error of the addition added to c (Neumaier's form of
+// Kahan summation: the error of the larger operand's sum is exact either way)
+__device__ __forceinline__ void comp_add(double &s, double &c, double x) {
+    const double t = s + x;
+    c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
+    s = t;
+}
+
 // every memory operation this wave issued has completed
 __device__ __forceinline__ void wait_stores() { __builtin_amdgcn_s_waitcnt(0); }
 
@@ -69,13 +79,13 @@ __device__ __forceinline__ bool reduce_blocks(const ReduceBufs &p, double *tot) 
 #pragma unroll
         for (int i = 0; i < kFinishGroup; ++i)
             v[i] = ld_dev(p.partials + (int64_t)(g0 + (i < gn ? i : gn - 1)) * PS + c);
-        double s = 0.0;
+        double s = 0.0, e = 0.0;
 #pragma unroll
         for (int i = 0; i < kFinishGroup; ++i) {
             const bool take = i < gn && ((g0 + i >= p.nb0) == (sg == 1));
-            s += take ? v[i] : 0.0;
+            comp_add(s, e, take ? v[i] : 0.0);
         }
-        st_dev(p.gsums + (int64_t)grp * 2 * PS + col, s);
+        st_dev(p.gsums + (int64_t)grp * 2 * PS + col, s + e);
     }
     if (tid == 0) __hip_atomic_store(&p.counters[1 + grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     wait_stores();
@@ -89,10 +99,10 @@ __device__ __forceinline__ bool reduce_blocks(const ReduceBufs &p, double *tot) 
     // column in thread order
     constexpr int NCOL = 2 * PS;
     constexpr int TPC = NT / NCOL > 0 ? NT / NCOL : 1;
-    __shared__ double part[NCOL * TPC];
+    __shared__ double part[NCOL * TPC], part_e[NCOL * TPC];
     for (int slot = tid; slot < NCOL * TPC; slot += NT) {
         const int col = slot / TPC, r = slot % TPC;
-        double s = 0.0;
+        double s = 0.0, e = 0.0;
         for (int gb = r; gb < ngroups; gb += 16 * TPC) {
             double v[16];
 #pragma unroll
@@ -101,16 +111,20 @@ __device__ __forceinline__ bool reduce_blocks(const ReduceBufs &p, double *tot) 
                 v[u] = ld_dev(p.gsums + (int64_t)(gi < ngroups ? gi : ngroups - 1) * NCOL + col);
             }
 #pragma unroll
-            for (int u = 0; u < 16; ++u) s += gb + u * TPC < ngroups ? v[u] : 0.0;
+            for (int u = 0; u < 16; ++u) comp_add(s, e, gb + u * TPC < ngroups ? v[u] : 0.0);
         }
         part[slot] = s;
+        part_e[slot] = e;
     }
     if (tid == 0) __hip_atomic_store(&p.counters[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     for (int col = tid; col < NCOL; col += NT) {
-        double s = 0.0;
-        for (int r = 0; r < TPC; ++r) s += part[col * TPC + r];
-        tot[col] = s;
+        double s = 0.0, e = 0.0;
+        for (int r = 0; r < TPC; ++r) {
+            comp_add(s, e, part[col * TPC + r]);
+            e += part_e[col * TPC + r];
+        }
+        tot[col] = s + e;
     }
     __syncthreads();
     return true;

@@ -19,7 +19,7 @@ Usage (from the repository root):
   python -m paper_1108_5882_amd.profile_summary counters DIR --kernel REGEX
       --title TEXT --command "CMD" --out profiles/NAME.md
   python -m paper_1108_5882_amd.profile_summary traffic FETCH_DIR WRITE_DIR --kernel REGEX
-      --last N --copy-bytes B --alg-bytes B --units U --config TEXT --source FILE
+      --last N --copy-bytes B --alg-bytes B --units U --config TEXT --source FILE [--source FILE ...]
       --command "CMD1" --command "CMD2" --out profiles/NAME  (writes NAME.md and NAME.json)
 """
 from __future__ import annotations
@@ -160,8 +160,11 @@ def write_traffic(args):
     fscale = args.copy_bytes / (cfk * 1024.0)
     wscale = args.copy_bytes / (cwk * 1024.0)
     hbm = fk * 1024.0 * fscale + wk * 1024.0 * wscale
-    with open(args.source, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in args.source:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    sha = h.hexdigest()[:16]
     rec = {"kernel": args.config, "dispatch_name": kname, "kernel_sha256_16": sha, "units_per_launch": args.units,
            "fetch_size_kib": fk, "write_size_kib": wk, "copy_bytes": args.copy_bytes, "copy_fetch_kib": cfk,
            "copy_write_kib": cwk, "fetch_scale": fscale, "write_scale": wscale, "hbm_bytes_per_launch": hbm,
@@ -207,7 +210,8 @@ def main(argv=None):
     p.add_argument("--alg-bytes", type=float, required=True)
     p.add_argument("--units", type=int, required=True)
     p.add_argument("--config", required=True)
-    p.add_argument("--source", required=True)
+    p.add_argument("--source", action="append", required=True,
+                   help="kernel source file; repeat for each file, in the order the bench hashes them")
     p.add_argument("--title", default="")
     p.add_argument("--command", action="append", default=[])
     p.add_argument("--out", required=True)
