@@ -34,6 +34,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 
 #include "block_reduce.hpp"
 #include "internal.hpp"
@@ -171,9 +172,12 @@ __global__ __launch_bounds__(kKinThreads) void kin_kernel(KinArgs p) {
         kin_n = mx[e0];
         w_n = Wl[e0];
     }
-    for (; t < ntiles; t += stride) {
-        const int64_t e = t * G + g;
-        const bool valid = e < n;
+    // Tiles below n / G hold no event past the sample: their steps need no
+    // per-event check, and only the last, partial tile (one wave's step at
+    // most) takes it.
+    const int64_t nfull = n / G;
+    auto event_step = [&](auto check) {
+        const bool valid = !decltype(check)::value || t * G + g < n;
         const float2 kin = kin_n;
         const float wf = has_w ? w_n : 1.0f;
         {
@@ -234,7 +238,9 @@ __global__ __launch_bounds__(kKinThreads) void kin_kernel(KinArgs p) {
             gg[q] = fma(bim[q], gr_, gg[q]);
             gg[q] = fma(-bre[q], gi_, gg[q]);
         }
-    }
+    };
+    for (; t < nfull; t += stride) event_step(std::false_type{});
+    for (; t < ntiles; t += stride) event_step(std::true_type{});
     if (seg == 0) acc_t += log(pm) + (double)pe * 0.69314718055994530942;
 
     // lanes with the same j across the wave's event groups
